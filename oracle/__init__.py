@@ -1,0 +1,232 @@
+"""CPU FP64 oracle for the batched 2-D panel method (test infrastructure).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark use
+this package.  The product library never imports, links or calls it, and it
+shares no code with the GPU path.  The arithmetic lives in plain C in
+``panel_oracle.c`` (each function cites the passage of the paper it follows);
+this module compiles it with gcc and marshals numpy arrays through ctypes.
+
+Parity status per function (see the pins under ``tests/``):
+  oracle_naca4          pinned (standard NACA 4-digit values, symmetry, LE/TE)
+  oracle_g_entry        pinned (adaptive quadrature of the defining integral)
+  oracle_assemble       pinned (entry-wise vs quadrature; Kutta row vs the
+                        Kutta-substituted system of Sec. 2)
+  oracle_lu / _solve    pinned (LAPACK getrf/getrs; hand-checked 3x3)
+  oracle_lu_solve_t     pinned (LAPACK transposed solve)
+  oracle_forces         pinned (cylinder Cp = 1 - 4 sin^2, lifting cylinder
+                        Cl = 4 pi sin alpha, Joukowski circulation, symmetric
+                        sections at zero incidence, the paper's C_L tables)
+  oracle_cl_gradient    pinned (central differences, exact discrete
+                        invariants: translation, scaling, rotation)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = [os.path.join(_HERE, "panel_oracle.c"), os.path.join(_HERE, "panel_oracle_grad.c")]
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (IEEE double, no FMA contraction, OpenMP)."""
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    srcs = [s for s in _SRC if os.path.exists(s)]
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-shared", "-fPIC", "-o", tmp] + srcs + ["-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or any(os.path.getmtime(s) > os.path.getmtime(_LIB)
+                                           for s in _SRC if os.path.exists(s)):
+            build()
+        L = C.CDLL(_LIB)
+        L.oracle_naca4.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, _dp]
+        L.oracle_naca4.restype = None
+        L.oracle_naca4_spaced.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                                          C.c_int, _dp]
+        L.oracle_naca4_spaced.restype = None
+        L.oracle_g_entry.argtypes = [_dp, C.c_int, C.c_int]
+        L.oracle_g_entry.restype = C.c_double
+        L.oracle_assemble.argtypes = [C.c_int, _dp, C.c_int, _dp, C.c_double, _dp, _dp]
+        L.oracle_assemble.restype = None
+        L.oracle_lu.argtypes = [C.c_int, _dp, _ip]
+        L.oracle_lu.restype = C.c_int
+        L.oracle_lu_solve.argtypes = [C.c_int, _dp, _ip, C.c_int, _dp]
+        L.oracle_lu_solve.restype = None
+        L.oracle_lu_solve_t.argtypes = [C.c_int, _dp, _ip, _dp]
+        L.oracle_lu_solve_t.restype = None
+        L.oracle_forces.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp, C.c_double, C.c_double,
+                                    _dp, _dp, _dp, _dp]
+        L.oracle_forces.restype = None
+        L.oracle_solve_airfoil.argtypes = [C.c_int, _dp, C.c_int, _dp, C.c_double, C.c_double,
+                                           _dp, _dp, _dp, _dp]
+        L.oracle_solve_airfoil.restype = C.c_int
+        L.oracle_solve_batch.argtypes = [C.c_int, _ip, _dp, _ip, _dp, C.c_void_p, C.c_double,
+                                         _dp, _dp, _dp, _dp, _ip, C.c_int]
+        L.oracle_solve_batch.restype = C.c_int
+        if hasattr(L, "oracle_cl_gradient"):
+            L.oracle_cl_gradient.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_double,
+                                             _dp, _dp]
+            L.oracle_cl_gradient.restype = C.c_int
+            L.oracle_naca4_jacobian.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int,
+                                                C.c_int, _dp]
+            L.oracle_naca4_jacobian.restype = None
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Single-airfoil helpers
+# ---------------------------------------------------------------------------
+
+def naca4(m, p, t, N, closed_te=True, uniform=False) -> np.ndarray:
+    """Nodes [N+1, 2] of a NACA 4-digit section, cosine (or uniform-x) spacing."""
+    if N % 2:
+        raise ValueError("N must be even")
+    xy = np.zeros(2 * (N + 1))
+    lib().oracle_naca4_spaced(float(m), float(p), float(t), int(N), int(bool(closed_te)),
+                              int(bool(uniform)), xy)
+    return xy.reshape(N + 1, 2)
+
+
+def g_entry(xy, j, i) -> float:
+    return lib().oracle_g_entry(_f64(xy).reshape(-1), int(j), int(i))
+
+
+def assemble(xy, alpha, vinf=1.0):
+    """Bordered matrix M [(N+1),(N+1)] and right-hand sides R [K, N+1]."""
+    xy = _f64(xy).reshape(-1)
+    N = xy.size // 2 - 1
+    alpha = _f64(np.atleast_1d(alpha))
+    K = alpha.size
+    M = np.zeros((N + 1) * (N + 1))
+    R = np.zeros((N + 1) * K)
+    lib().oracle_assemble(N, xy, K, alpha, float(vinf), M, R)
+    return M.reshape(N + 1, N + 1), R.reshape(K, N + 1)
+
+
+def lu(A):
+    """(LU, piv, info) of a square matrix with partial pivoting."""
+    A = _f64(A).copy()
+    n = A.shape[0]
+    piv = np.zeros(n, dtype=np.int32)
+    info = lib().oracle_lu(n, A.reshape(-1), piv)
+    return A, piv, info
+
+
+def lu_solve(LU, piv, Bm):
+    """Solve with K right-hand sides given as rows of Bm [K, n]."""
+    LU = _f64(LU)
+    X = _f64(np.atleast_2d(Bm)).copy()
+    n = LU.shape[0]
+    lib().oracle_lu_solve(n, LU.reshape(-1), np.ascontiguousarray(piv, dtype=np.int32),
+                          X.shape[0], X.reshape(-1))
+    return X
+
+
+def lu_solve_t(LU, piv, w):
+    LU = _f64(LU)
+    y = _f64(w).copy()
+    lib().oracle_lu_solve_t(LU.shape[0], LU.reshape(-1), np.ascontiguousarray(piv, dtype=np.int32), y)
+    return y
+
+
+def forces(xy, alpha, X, vinf=1.0, chord=1.0):
+    xy = _f64(xy).reshape(-1)
+    N = xy.size // 2 - 1
+    alpha = _f64(np.atleast_1d(alpha))
+    K = alpha.size
+    X = _f64(np.atleast_2d(X))
+    gamma = np.zeros(K * N)
+    cp = np.zeros(K * N)
+    cl = np.zeros(K)
+    clp = np.zeros(K)
+    lib().oracle_forces(N, xy, K, alpha, X.reshape(-1), float(vinf), float(chord), gamma, cp, cl, clp)
+    return gamma.reshape(K, N), cp.reshape(K, N), cl, clp
+
+
+def solve_airfoil(xy, alpha, vinf=1.0, chord=1.0):
+    """Whole pipeline for one airfoil: dict(gamma[K,N], cp[K,N], cl[K], cl_p[K], info)."""
+    xy = _f64(xy).reshape(-1)
+    N = xy.size // 2 - 1
+    alpha = _f64(np.atleast_1d(alpha))
+    K = alpha.size
+    gamma = np.zeros(K * N)
+    cp = np.zeros(K * N)
+    cl = np.zeros(K)
+    clp = np.zeros(K)
+    info = lib().oracle_solve_airfoil(N, xy, K, alpha, float(vinf), float(chord), gamma, cp, cl, clp)
+    return dict(gamma=gamma.reshape(K, N), cp=cp.reshape(K, N), cl=cl, cl_p=clp, info=info)
+
+
+def solve_batch(xy_flat, node_off, alpha_flat, alpha_off, chord=None, vinf=1.0, nthreads=0):
+    """Batch in the packed layout of the GPU library (see panel_oracle.c)."""
+    node_off = np.ascontiguousarray(node_off, dtype=np.int32)
+    alpha_off = np.ascontiguousarray(alpha_off, dtype=np.int32)
+    B = node_off.size - 1
+    Ns = np.diff(node_off) - 1
+    Ks = np.diff(alpha_off)
+    tot = int(np.sum(Ns.astype(np.int64) * Ks))
+    gamma = np.zeros(tot)
+    cp = np.zeros(tot)
+    cl = np.zeros(int(alpha_off[-1]))
+    clp = np.zeros(int(alpha_off[-1]))
+    info = np.zeros(B, dtype=np.int32)
+    ch = None
+    if chord is not None:
+        chord = _f64(chord)
+        ch = chord.ctypes.data_as(C.c_void_p)
+    used = lib().oracle_solve_batch(B, node_off, _f64(xy_flat).reshape(-1), alpha_off,
+                                    _f64(alpha_flat), ch, float(vinf), gamma, cp, cl, clp, info,
+                                    int(nthreads))
+    return dict(gamma=gamma, cp=cp, cl=cl, cl_p=clp, info=info, threads=used)
+
+
+def cl_gradient(xy, alpha, vinf=1.0, chord=1.0, with_alpha=False):
+    """dCl/dP for all N+1 nodes (Cl by circulation, chord held fixed): [N+1, 2].
+
+    With ``with_alpha`` also returns dCl/dalpha."""
+    xy = _f64(xy).reshape(-1)
+    N = xy.size // 2 - 1
+    g = np.zeros(2 * (N + 1))
+    da = np.zeros(1)
+    info = lib().oracle_cl_gradient(N, xy, float(alpha), float(vinf), float(chord), g, da)
+    if info != 0:
+        raise RuntimeError(f"oracle gradient failed, info={info}")
+    if with_alpha:
+        return g.reshape(N + 1, 2), float(da[0])
+    return g.reshape(N + 1, 2)
+
+
+def naca4_jacobian(m, p, t, N, closed_te=True) -> np.ndarray:
+    """d(node coordinates)/d(m, p, t): [N+1, 2, 3]."""
+    J = np.zeros(2 * (N + 1) * 3)
+    lib().oracle_naca4_jacobian(float(m), float(p), float(t), int(N), int(bool(closed_te)), J)
+    return J.reshape(N + 1, 2, 3)
+
+
+def workload_nodes(w):
+    """Oracle-side NACA nodes for a synth.Workload: (xy_flat, node_offsets)."""
+    parts = [naca4(w.m[b], w.p[b], w.t[b], int(w.n_panels[b]), w.closed_te) for b in range(w.B)]
+    xy = np.concatenate([q.reshape(-1) for q in parts])
+    return xy, w.node_offsets()
