@@ -1,0 +1,187 @@
+/*
+ * panel.h -- C ABI of the batched 2-D panel-method library for AMD MI355X
+ * (gfx950).  Reference method: Einkemmer, arXiv:1511.02166, Sec. 2
+ * ("Numerical algorithm") and Sec. 3 (assembly O(n^2) with logarithms and
+ * arctangents, LU (2/3)n^3).
+ *
+ * A batch holds B airfoils.  Airfoil b has N_b panels between N_b + 1 nodes
+ * P_0..P_N (trailing edge first, counter-clockwise: upper surface, leading
+ * edge, lower surface; P_N = P_0 for a closed section) and K_b angles of
+ * attack.  For each airfoil the library assembles the bordered
+ * (N_b + 1) x (N_b + 1) system of Sec. 2
+ *     sum_i G_ji gamma_i - C = -phi_v(m_j)      (j < N_b, midpoints m_j)
+ *     gamma_0 + gamma_{N_b - 1} = 0              (Kutta condition)
+ * with G_ji the integral of -(1/2pi) log|m_j - s| over panel i, factors it
+ * once by LU with partial pivoting, solves it for the K_b right-hand sides
+ * phi_v = vinf (y cos alpha - x sin alpha), and reduces the surface speed
+ * gamma_i, Cp_i = 1 - (gamma_i / vinf)^2 and the lift coefficient.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers unless the name starts with h_.
+ *    Every floating-point array is IEEE double, 8-byte aligned.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls that take a stream only enqueue work on it: they never
+ *    synchronise the device and never allocate device memory, so the
+ *    sequence assemble -> factor_solve -> forces may be captured into a
+ *    HIP graph.
+ *  - The caller owns all device memory, including the workspace, whose size
+ *    panel_workspace_size reports.  The library keeps no device pointers
+ *    between calls.  A plan owns host memory only.
+ *  - Return value: PANEL_OK, or an error code.  Argument checks run on the
+ *    host before any HIP call; on failure nothing is enqueued and
+ *    panel_last_error() (thread-local) describes the problem.
+ *  - Per-airfoil outcomes are reported on the device in info[b]:
+ *       0   success
+ *       k>0 exact zero pivot in column k (1-based, LAPACK getrf convention);
+ *           that airfoil's outputs are NaN
+ *      -1   non-finite node coordinate or zero-length panel; outputs NaN
+ *      -2   mixed precision: refinement did not reach the tolerance within
+ *           max_iter sweeps (the last iterate is returned)
+ */
+#ifndef PANEL_H
+#define PANEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PANEL_OK = 0,
+    PANEL_EINVAL = 1,       /* bad argument (reported before any HIP call)  */
+    PANEL_ENOMEM = 2,       /* host allocation failed                        */
+    PANEL_EHIP = 3,         /* a HIP runtime call or kernel launch failed    */
+    PANEL_EUNSUPPORTED = 4  /* valid request this build does not support     */
+} panel_status;
+
+typedef enum {
+    PANEL_FP64 = 0,         /* FP64 assembly, FP64 LU and solve              */
+    PANEL_FP32_REFINE = 1   /* FP64 assembly; FP32 LU; FP64 residual-based
+                               iterative refinement of the solution          */
+} panel_precision;
+
+/* Largest supported panel count per airfoil. */
+#define PANEL_NMAX 1024
+/* Smallest supported panel count per airfoil. */
+#define PANEL_NMIN 4
+/* Largest supported number of angles of attack per airfoil. */
+#define PANEL_KMAX 16
+
+typedef struct panel_plan panel_plan;
+
+/* Create a plan for a batch (host metadata only; no HIP call).
+ *   B                 number of airfoils, B >= 1
+ *   h_node_offsets    host int32[B+1], nondecreasing, [0] = 0; airfoil b owns
+ *                     nodes h_node_offsets[b] .. h_node_offsets[b+1]-1, i.e.
+ *                     N_b = diff - 1 panels, PANEL_NMIN <= N_b <= PANEL_NMAX
+ *   h_alpha_offsets   host int32[B+1], [0] = 0; K_b = diff,
+ *                     1 <= K_b <= PANEL_KMAX
+ *   precision         a panel_precision value
+ *   out               receives the plan (release with panel_plan_destroy)
+ * The offsets are copied; the caller may free them afterwards.            */
+panel_status panel_plan_create(int32_t B, const int32_t *h_node_offsets,
+                               const int32_t *h_alpha_offsets, int32_t precision,
+                               panel_plan **out);
+
+/* Release a plan (NULL is ignored). */
+void panel_plan_destroy(panel_plan *plan);
+
+/* Bytes of device workspace the plan needs (256-byte aligned base). */
+panel_status panel_workspace_size(const panel_plan *plan, size_t *bytes);
+
+/* Where airfoil b's data sit inside a workspace (for inspection and tests):
+ * h_desc receives 8 int64 values: byte offsets of the FP64 augmented system
+ * (column-major, ld rows, n1 + K columns), of the FP32 system (-1 unless
+ * PANEL_FP32_REFINE), of the K solutions, of the n1 int32 pivots, then n1,
+ * ld, K, and the byte offset of the int32 refinement-sweep counter.        */
+panel_status panel_workspace_layout(const panel_plan *plan, int32_t b, int64_t *h_desc);
+
+/* Write the plan's per-airfoil metadata into the workspace (one host-to-
+ * device copy on `stream`).  Must precede the first panel_assemble on a
+ * workspace; the metadata stays valid until the workspace is reused for
+ * another plan.  Not meant to be captured in a graph.                      */
+panel_status panel_workspace_init(const panel_plan *plan, void *ws, void *stream);
+
+/* Assembly (Sec. 2: panel integrals at the midpoints, the constant C, the
+ * Kutta row, free-stream right-hand sides).  Everything in FP64; with
+ * PANEL_FP32_REFINE an FP32 copy of the system is also written for the
+ * factorisation.
+ *   xy      2 * node_offsets[B] doubles, node k of the batch at (xy[2k], xy[2k+1])
+ *   alpha   alpha_offsets[B] angles of attack in radians
+ *   chord   B reference lengths for the lift coefficient, or NULL (all 1)
+ *   vinf    free-stream speed, finite and > 0
+ *   ws      workspace of panel_workspace_size bytes, initialised          */
+panel_status panel_assemble(const panel_plan *plan, const double *xy, const double *alpha,
+                            const double *chord, double vinf, void *ws, void *stream);
+
+/* LU factorisation with partial pivoting (largest |a_ik|, lowest row index
+ * on ties) of every assembled system, and solution for its K_b right-hand
+ * sides (Sec. 3: LU, (2/3)n^3 operations).  With PANEL_FP32_REFINE the
+ * factorisation is in FP32 and the solution is refined: r = b - A x in
+ * FP64, correction from the FP32 factors, x += correction, until
+ * ||correction||_inf <= refine_tol * ||x||_inf, or until the residual sits at
+ * the FP64 backward-error floor ||r||_inf <= sqrt(n) eps ||A||_inf ||x||_inf
+ * (no sweep can improve x further), or max_iter sweeps (info -2).
+ * max_iter = 0 disables refinement and reports -2 (result unverified).
+ *   refine_tol  > 0 (ignored for PANEL_FP64)
+ *   max_iter    0..100 (ignored for PANEL_FP64)
+ *   info        device int32[B], written per airfoil (codes above)        */
+panel_status panel_factor_solve(const panel_plan *plan, void *ws, double refine_tol,
+                                int32_t max_iter, int32_t *info, void *stream);
+
+/* Surface speed, pressure coefficient and lift (forces step; the paper
+ * reports C_L without printing its formula):
+ *   gamma[s_b + k N_b + i] = gamma_i   (tangential speed, CCW tangent)
+ *   cp   [s_b + k N_b + i] = 1 - (gamma_i / vinf)^2
+ *   cl   [alpha_offsets[b] + k] = -2 sum_i gamma_i L_i / (vinf c_b)
+ *   cl_p [alpha_offsets[b] + k] = -(1/c_b) sum_i Cp_i L_i (n_i . e_L),
+ *          n_i outward normal, e_L = (-sin alpha, cos alpha)
+ * with s_b = sum_{b'<b} N_b' K_b'.  gamma, cp, cl_p may be NULL.          */
+panel_status panel_forces(const panel_plan *plan, const void *ws, double *gamma, double *cp,
+                          double *cl, double *cl_p, void *stream);
+
+/* Reverse-mode sensitivity of the lift (cl above) to every node:
+ *   dxy[2k + c] = sum over the airfoil's angles of dcl[.] * dCl/dP_k,c
+ * for all N_b + 1 nodes of each airfoil (node 0 and node N are separate
+ * variables).  Uses the factors left in the workspace by
+ * panel_factor_solve (transposed solve; refined in FP64 for
+ * PANEL_FP32_REFINE) and re-evaluates the assembly derivatives on the fly.
+ *   xy     the node array passed to panel_assemble
+ *   dcl    alpha_offsets[B] cotangents of cl
+ *   dxy    2 * node_offsets[B] doubles, overwritten
+ * Airfoils with info != 0 get NaN.                                         */
+panel_status panel_adjoint(const panel_plan *plan, const void *ws, const double *xy,
+                           const double *dcl, double *dxy, void *stream);
+
+/* NACA 4-digit sections (geometry helper for the GA population): cosine
+ * spacing x = (1 + cos(pi s / (N/2)))/2, s = min(k, N - k), nodes 0..N/2 on
+ * the upper surface; thickness coefficient a4 = -0.1036 (closed_te != 0,
+ * node N = node 0) or -0.1015.
+ *   B         number of sections
+ *   node_off  DEVICE int32[B+1] node offsets (N_b even, 4..PANEL_NMAX)
+ *   mpt       B x 3 doubles (max camber m, its position p in (0,1),
+ *             thickness t)
+ *   xy        2 * node_off[B] doubles, written                             */
+panel_status panel_naca4(int32_t B, const int32_t *node_off, int32_t closed_te,
+                         const double *mpt, double *xy, void *stream);
+
+/* Vector-Jacobian product of panel_naca4:
+ *   dmpt[3b + q] = sum_k dxy[2k + c] * d xy[2k + c] / d mpt[3b + q]
+ * over the nodes of section b (the node-N entry of a closed section is
+ * routed to node 0, of which it is a copy).                                */
+panel_status panel_naca4_vjp(int32_t B, const int32_t *node_off, int32_t closed_te,
+                             const double *mpt, const double *dxy, double *dmpt, void *stream);
+
+/* Static description of a status code. */
+const char *panel_status_str(int32_t status);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char *panel_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PANEL_H */

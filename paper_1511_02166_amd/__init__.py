@@ -1,0 +1,44 @@
+"""Batched 2-D panel-method solver for AMD MI355X (gfx950).
+
+Thin Python binding over the C ABI of ``libpanel.so`` (declared in
+``include/panel.h``).  Every step of the computation runs in the HIP
+kernels of that library; this package only marshals arguments (device
+pointers of torch tensors, the current HIP stream) and raises on errors.
+There is no CPU fallback: if the library is missing, importing the binding
+functions raises.
+"""
+from __future__ import annotations
+
+from ._binding import (  # noqa: F401
+    PANEL_FP32_REFINE,
+    PANEL_FP64,
+    PANEL_KMAX,
+    PANEL_NMAX,
+    PANEL_NMIN,
+    PanelError,
+    Plan,
+    lib_path,
+    load_library,
+    panel_adjoint,
+    panel_assemble,
+    panel_factor_solve,
+    panel_forces,
+    panel_last_error,
+    panel_naca4,
+    panel_naca4_vjp,
+    panel_plan_create,
+    panel_plan_destroy,
+    panel_status_str,
+    panel_workspace_init,
+    panel_workspace_layout,
+    panel_workspace_size,
+)
+from .solver import PanelSolver, panel_cl, naca_cl  # noqa: F401
+
+__all__ = [
+    "PANEL_FP64", "PANEL_FP32_REFINE", "PANEL_NMAX", "PANEL_NMIN", "PANEL_KMAX",
+    "PanelError", "Plan", "PanelSolver", "panel_cl", "naca_cl",
+    "panel_plan_create", "panel_plan_destroy", "panel_workspace_size", "panel_workspace_init", "panel_workspace_layout",
+    "panel_assemble", "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
+    "panel_naca4_vjp", "panel_status_str", "panel_last_error", "load_library", "lib_path",
+]

@@ -1,0 +1,216 @@
+"""ctypes marshalling for the C ABI in include/panel.h (same names)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libpanel.so")
+
+PANEL_OK, PANEL_EINVAL, PANEL_ENOMEM, PANEL_EHIP, PANEL_EUNSUPPORTED = range(5)
+PANEL_FP64, PANEL_FP32_REFINE = 0, 1
+PANEL_NMAX, PANEL_NMIN, PANEL_KMAX = 1024, 4, 16
+
+_lib = None
+
+
+class PanelError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{panel_status_str(status)}: {msg}")
+        self.status = status
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libpanel.so (built in-tree by ``python -m paper_1511_02166_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                           "`python -m paper_1511_02166_amd.build` (no CPU fallback exists)")
+    L = C.CDLL(_LIB_PATH)
+    vp, i32, f64, sz = C.c_void_p, C.c_int32, C.c_double, C.c_size_t
+    L.panel_plan_create.argtypes = [i32, vp, vp, i32, C.POINTER(vp)]
+    L.panel_plan_destroy.argtypes = [vp]
+    L.panel_plan_destroy.restype = None
+    L.panel_workspace_size.argtypes = [vp, C.POINTER(sz)]
+    L.panel_workspace_init.argtypes = [vp, vp, vp]
+    L.panel_workspace_layout.argtypes = [vp, i32, vp]
+    L.panel_assemble.argtypes = [vp, vp, vp, vp, f64, vp, vp]
+    L.panel_factor_solve.argtypes = [vp, vp, f64, i32, vp, vp]
+    L.panel_forces.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.panel_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.panel_naca4.argtypes = [i32, vp, i32, vp, vp, vp]
+    L.panel_naca4_vjp.argtypes = [i32, vp, i32, vp, vp, vp, vp]
+    L.panel_status_str.argtypes = [i32]
+    L.panel_status_str.restype = C.c_char_p
+    L.panel_last_error.argtypes = []
+    L.panel_last_error.restype = C.c_char_p
+    for name in ("panel_plan_create", "panel_workspace_size", "panel_workspace_init",
+                 "panel_workspace_layout", "panel_assemble",
+                 "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
+                 "panel_naca4_vjp"):
+        getattr(L, name).restype = C.c_int32
+    _lib = L
+    return L
+
+
+def panel_status_str(status: int) -> str:
+    return load_library().panel_status_str(int(status)).decode()
+
+
+def panel_last_error() -> str:
+    return load_library().panel_last_error().decode()
+
+
+def _check(status: int):
+    if status != PANEL_OK:
+        raise PanelError(status, panel_last_error())
+
+
+def _ptr(t, dtype=None, name="array", allow_none=False):
+    """Device pointer of a contiguous CUDA/HIP torch tensor (or None)."""
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU (got {t.device})")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """Owner of a ``panel_plan*`` (host metadata for one batch layout)."""
+
+    def __init__(self, node_offsets, alpha_offsets, precision=PANEL_FP64):
+        L = load_library()
+        no = np.ascontiguousarray(node_offsets, dtype=np.int32)
+        ao = np.ascontiguousarray(alpha_offsets, dtype=np.int32)
+        if no.ndim != 1 or ao.ndim != 1 or no.size != ao.size or no.size < 2:
+            raise ValueError("node_offsets and alpha_offsets must be 1-D int arrays of length B+1")
+        self.B = int(no.size - 1)
+        self.node_offsets = no
+        self.alpha_offsets = ao
+        self.precision = int(precision)
+        h = C.c_void_p()
+        _check(L.panel_plan_create(self.B, no.ctypes.data_as(C.c_void_p), ao.ctypes.data_as(C.c_void_p),
+                                   self.precision, C.byref(h)))
+        self._h = h
+        self.n_nodes = int(no[-1])
+        self.n_alpha = int(ao[-1])
+        n = np.diff(no).astype(np.int64) - 1
+        k = np.diff(ao).astype(np.int64)
+        self.n_panels = n
+        self.n_angles = k
+        self.n_out = int(np.sum(n * k))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_size(self) -> int:
+        out = C.c_size_t()
+        _check(load_library().panel_workspace_size(self._h, C.byref(out)))
+        return int(out.value)
+
+    def layout(self, b: int) -> dict:
+        d = np.zeros(8, dtype=np.int64)
+        _check(load_library().panel_workspace_layout(self._h, int(b), d.ctypes.data_as(C.c_void_p)))
+        return dict(a64=int(d[0]), a32=int(d[1]), x=int(d[2]), piv=int(d[3]), n1=int(d[4]),
+                    ld=int(d[5]), K=int(d[6]), iters=int(d[7]))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.panel_plan_destroy(h)
+            self._h = None
+
+
+# -- functions with the C ABI's names ---------------------------------------
+
+def panel_plan_create(node_offsets, alpha_offsets, precision=PANEL_FP64) -> Plan:
+    return Plan(node_offsets, alpha_offsets, precision)
+
+
+def panel_plan_destroy(plan: Plan):
+    if plan._h is not None and plan._h.value:
+        load_library().panel_plan_destroy(plan._h)
+    plan._h = None
+
+
+def panel_workspace_size(plan: Plan) -> int:
+    return plan.workspace_size()
+
+
+def panel_workspace_layout(plan: Plan, b: int) -> dict:
+    return plan.layout(b)
+
+
+def panel_workspace_init(plan: Plan, ws, stream=None):
+    import torch
+    _check(load_library().panel_workspace_init(plan.handle, _ptr(ws, torch.uint8, "ws"), _stream(stream)))
+
+
+def panel_assemble(plan: Plan, xy, alpha, chord, vinf, ws, stream=None):
+    import torch
+    d = torch.float64
+    _check(load_library().panel_assemble(plan.handle, _ptr(xy, d, "xy"), _ptr(alpha, d, "alpha"),
+                                         _ptr(chord, d, "chord", True), float(vinf),
+                                         _ptr(ws, torch.uint8, "ws"), _stream(stream)))
+
+
+def panel_factor_solve(plan: Plan, ws, refine_tol, max_iter, info, stream=None):
+    import torch
+    _check(load_library().panel_factor_solve(plan.handle, _ptr(ws, torch.uint8, "ws"), float(refine_tol),
+                                             int(max_iter), _ptr(info, torch.int32, "info"),
+                                             _stream(stream)))
+
+
+def panel_forces(plan: Plan, ws, gamma, cp, cl, cl_p, stream=None):
+    import torch
+    d = torch.float64
+    _check(load_library().panel_forces(plan.handle, _ptr(ws, torch.uint8, "ws"),
+                                       _ptr(gamma, d, "gamma", True), _ptr(cp, d, "cp", True),
+                                       _ptr(cl, d, "cl"), _ptr(cl_p, d, "cl_p", True), _stream(stream)))
+
+
+def panel_adjoint(plan: Plan, ws, xy, dcl, dxy, stream=None):
+    import torch
+    d = torch.float64
+    _check(load_library().panel_adjoint(plan.handle, _ptr(ws, torch.uint8, "ws"), _ptr(xy, d, "xy"),
+                                        _ptr(dcl, d, "dcl"), _ptr(dxy, d, "dxy"), _stream(stream)))
+
+
+def panel_naca4(B, node_off, closed_te, mpt, xy, stream=None):
+    import torch
+    _check(load_library().panel_naca4(int(B), _ptr(node_off, torch.int32, "node_off"), int(bool(closed_te)),
+                                      _ptr(mpt, torch.float64, "mpt"), _ptr(xy, torch.float64, "xy"),
+                                      _stream(stream)))
+
+
+def panel_naca4_vjp(B, node_off, closed_te, mpt, dxy, dmpt, stream=None):
+    import torch
+    d = torch.float64
+    _check(load_library().panel_naca4_vjp(int(B), _ptr(node_off, torch.int32, "node_off"),
+                                          int(bool(closed_te)), _ptr(mpt, d, "mpt"), _ptr(dxy, d, "dxy"),
+                                          _ptr(dmpt, d, "dmpt"), _stream(stream)))

@@ -1,0 +1,543 @@
+// lu.hip -- batched LU factorisation with partial pivoting, triangular
+// solves and mixed-precision iterative refinement on gfx950.
+//
+// Sec. 3 of the paper: each airfoil needs an LU decomposition of its dense
+// system ((2/3)n^3 operations), and many small systems are solved at once.
+// One workgroup (4 waves) factors one airfoil's augmented matrix [M | rhs]
+// in place, right-looking and blocked by NB columns:
+//   1. the n - k0 rows of the NB-column panel are held in registers, one row
+//      per thread; each column step finds the pivot with a wavefront
+//      shuffle reduction plus a 4-entry LDS reduction (largest |a|, lowest
+//      row index on ties), exchanges the two rows through LDS, scales and
+//      applies the rank-1 update to the thread's own rows;
+//   2. the row exchanges are applied to every other column (each thread
+//      owns whole columns, so the exchanges of one panel run sequentially
+//      per column without synchronisation);
+//   3. U12 = L11^{-1} A12 (one thread per column, L11 broadcast from LDS);
+//   4. A22 -= L21 U12 on the matrix cores (v_mfma 16x16x4 in FP64 or FP32),
+//      U12 staged in LDS, C tiles streamed from global memory.
+// The right-hand-side columns ride along as extra columns, so after the
+// factorisation they hold L^{-1} P b; the same workgroup then finishes with
+// the back substitution (blocked: one wavefront solves each 64-row diagonal
+// block with shuffles, all four update the rows above).
+#include <climits>
+
+#include "panel_internal.hpp"
+
+namespace panel {
+namespace {
+
+constexpr int TPB = 256;   // threads per workgroup (4 wavefronts)
+constexpr int CH = 256;    // trailing columns per U12 chunk
+constexpr int SB = 64;     // rows per diagonal block in the triangular solves
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// D = A(16x4) B(4x16) + C.  Lane l supplies A[l%16][l/16] and B[l/16][l%16].
+// Element v of lane l holds D[row(l, v)][l%16]; the row map differs between
+// the two instructions (measured on gfx950): FP64 interleaves the four row
+// groups, FP32 keeps each lane's four rows consecutive.
+template <typename T> struct Acc;
+template <> struct Acc<double> {
+    typedef d4_t type;
+    static __device__ inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <> struct Acc<float> {
+    typedef f4_t type;
+    static __device__ inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+__device__ inline d4_t mfma16(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4_t mfma16(float a, float b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> __device__ inline T* sys_base(const WsView &v, const AirfoilMeta &mt);
+template <> __device__ inline double *sys_base<double>(const WsView &v, const AirfoilMeta &mt) {
+    return v.a64 + mt.a_off;
+}
+template <> __device__ inline float *sys_base<float>(const WsView &v, const AirfoilMeta &mt) {
+    return v.a32 + mt.a_off;
+}
+
+// Pivot candidate order: larger magnitude wins, lower row index on ties.
+__device__ inline bool better(double va, int ia, double vb, int ib) {
+    return va > vb || (va == vb && ia < ib);
+}
+
+// ---- triangular solves on one vector held in LDS ---------------------------
+
+// Back substitution U x = y (U upper, column-major in global memory), y in LDS.
+template <typename T, typename V>
+__device__ void trsv_upper(const T *U, int ld, int n, V *y) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nblk = (n + SB - 1) / SB;
+    for (int blk = nblk - 1; blk >= 0; --blk) {
+        const int rb = blk * SB, re = min(rb + SB, n);
+        if (wave == 0) {
+            const int r = rb + lane;
+            V yi = (r < re) ? y[r] : V(0);
+            for (int j = re - 1; j >= rb; --j) {
+                const V uij = (r < j) ? V(U[(size_t)j * ld + r]) : V(0);
+                V xj = (r == j) ? yi / V(U[(size_t)j * ld + j]) : V(0);
+                xj = __shfl(xj, j - rb);
+                if (r == j) yi = xj;
+                if (r < j) yi -= uij * xj;
+            }
+            if (r < re) y[r] = yi;
+        }
+        __syncthreads();
+        for (int r = tid; r < rb; r += TPB) {
+            V s = y[r];
+            for (int j = rb; j < re; ++j) s -= V(U[(size_t)j * ld + r]) * y[j];
+            y[r] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// Forward substitution L y = b (unit lower), y in LDS.
+template <typename T, typename V>
+__device__ void trsv_lower_unit(const T *L, int ld, int n, V *y) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nblk = (n + SB - 1) / SB;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int rb = blk * SB, re = min(rb + SB, n);
+        if (wave == 0) {
+            const int r = rb + lane;
+            V yi = (r < re) ? y[r] : V(0);
+            for (int j = rb; j < re; ++j) {
+                const V lij = (r > j && r < re) ? V(L[(size_t)j * ld + r]) : V(0);
+                const V xj = __shfl(yi, j - rb);
+                if (r > j) yi -= lij * xj;
+            }
+            if (r < re) y[r] = yi;
+        }
+        __syncthreads();
+        for (int r = re + tid; r < n; r += TPB) {
+            V s = y[r];
+            for (int j = rb; j < re; ++j) s -= V(L[(size_t)j * ld + r]) * y[j];
+            y[r] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// One column step of the panel factorisation: pivot search over rows
+// g..n-1 of column C, row exchange through LDS, scaling and rank-1 update of
+// the thread's own rows.  C is a template parameter so the register array p
+// is only ever indexed with constants.
+template <typename T, int NB, int R, int C>
+__device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int nb, int n, int &info,
+                                           T *s_prow, T *s_srow, double *s_cval, int *s_cidx,
+                                           int *s_piv) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = k0 + C;
+    double best = -1.0;
+    int bidx = INT_MAX;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = k0 + tid + TPB * q;
+        if (r >= g && r < n) {
+            const double a = fabs((double)p[q][C]);
+            if (a > best) {
+                best = a;
+                bidx = r;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bidx, off);
+        if (better(ob, oi, best, bidx)) {
+            best = ob;
+            bidx = oi;
+        }
+    }
+    if (lane == 0) {
+        s_cval[wave] = best;
+        s_cidx[wave] = bidx;
+    }
+    __syncthreads();
+    best = s_cval[0];
+    bidx = s_cidx[0];
+#pragma unroll
+    for (int w = 1; w < TPB / 64; ++w) {
+        if (better(s_cval[w], s_cidx[w], best, bidx)) {
+            best = s_cval[w];
+            bidx = s_cidx[w];
+        }
+    }
+    // best == 0: the column is zero at and below the diagonal (exact zero
+    // pivot); no candidate at all (NaN column) is treated alike.
+    const bool zero = !(best > 0.0) || bidx == INT_MAX;
+    const int pr = zero ? g : bidx;
+    const int pown = (pr - k0) & (TPB - 1), pq = (pr - k0) / TPB;
+    if (tid == pown) {
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (q == pq) {
+#pragma unroll
+                for (int cc = 0; cc < NB; ++cc) s_prow[cc] = p[q][cc];
+            }
+    }
+    if (tid == C) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) s_srow[cc] = p[0][cc];
+    }
+    if (tid == 0) s_piv[C] = pr;
+    __syncthreads();
+    if (!zero) {
+        if (pr != g) {
+            if (tid == pown) {
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    if (q == pq) {
+#pragma unroll
+                        for (int cc = 0; cc < NB; ++cc) p[q][cc] = s_srow[cc];
+                    }
+            }
+            if (tid == C) {
+#pragma unroll
+                for (int cc = 0; cc < NB; ++cc) p[0][cc] = s_prow[cc];
+            }
+        }
+        const T pv = s_prow[C];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = k0 + tid + TPB * q;
+            if (r > g && r < n) {
+                const T l = p[q][C] / pv;
+                p[q][C] = l;
+#pragma unroll
+                for (int cc = C + 1; cc < NB; ++cc) p[q][cc] -= l * s_prow[cc];
+            }
+        }
+    } else if (info == 0) {
+        info = g + 1;
+    }
+    __syncthreads();
+}
+
+template <typename T, int NB, int R, int C>
+__device__ __forceinline__ void panel_steps(T (&p)[R][NB], int k0, int nb, int n, int &info,
+                                            T *s_prow, T *s_srow, double *s_cval, int *s_cidx,
+                                            int *s_piv) {
+    if constexpr (C < NB) {
+        if (C < nb) {
+            panel_step<T, NB, R, C>(p, k0, nb, n, info, s_prow, s_srow, s_cval, s_cidx, s_piv);
+            panel_steps<T, NB, R, C + 1>(p, k0, nb, n, info, s_prow, s_srow, s_cval, s_cidx, s_piv);
+        }
+    }
+}
+
+template <typename T, int NB, int R>
+__global__ __launch_bounds__(TPB) void lu_kernel(WsView v, int32_t *__restrict__ info_out) {
+    const int b = v.order[blockIdx.x];
+    const AirfoilMeta mt = v.meta[b];
+    const int n = mt.n1, ld = mt.ld, ncols = mt.n1 + mt.K;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    if (v.flag[b] != 0) {   // screened out by the assembly
+        if (tid == 0) info_out[b] = -1;
+        double *X = v.x + mt.x_off;
+        for (int i = tid; i < n * mt.K; i += TPB) X[i] = __builtin_nan("");
+        return;
+    }
+
+    T *A = sys_base<T>(v, mt);
+    int32_t *piv = v.piv + mt.piv_off;
+
+    __shared__ T s_prow[NB];
+    __shared__ T s_srow[NB];
+    __shared__ T s_L11[NB][NB + 1];
+    __shared__ T s_U[NB][CH];
+    __shared__ double s_cval[TPB / 64];
+    __shared__ int s_cidx[TPB / 64];
+    __shared__ int s_piv[NB];
+    int info = 0;
+
+    T p[R][NB];
+
+    for (int k0 = 0; k0 < n; k0 += NB) {
+        const int nb = min(NB, n - k0);
+
+        // ---- 1. panel into registers (row k0 + tid + TPB*q) -------------
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = k0 + tid + TPB * q;
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc)
+                p[q][cc] = (r < n && cc < nb) ? A[(size_t)(k0 + cc) * ld + r] : T(0);
+        }
+
+        // ---- panel factorisation (column index fixed at compile time) ----
+        panel_steps<T, NB, R, 0>(p, k0, nb, n, info, s_prow, s_srow, s_cval, s_cidx, s_piv);
+
+        // ---- panel back to memory, L11 and pivots to LDS ----------------
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = k0 + tid + TPB * q;
+            if (r < n) {
+#pragma unroll
+                for (int cc = 0; cc < NB; ++cc)
+                    if (cc < nb) A[(size_t)(k0 + cc) * ld + r] = p[q][cc];
+            }
+        }
+        if (tid < NB) {
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc) s_L11[tid][cc] = (tid < nb) ? p[0][cc] : T(0);
+            if (tid < nb) piv[k0 + tid] = s_piv[tid];
+        }
+        __syncthreads();
+
+        // ---- 2. row exchanges on every column outside the panel -----------
+        for (int j = tid; j < ncols - nb; j += TPB) {
+            const int col = j < k0 ? j : j + nb;
+            T *cp = A + (size_t)col * ld;
+            for (int c = 0; c < nb; ++c) {
+                const int pr = s_piv[c];
+                const int g = k0 + c;
+                if (pr != g) {
+                    const T t0 = cp[g];
+                    cp[g] = cp[pr];
+                    cp[pr] = t0;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- 3./4. U12 and the trailing update, CH columns at a time -----
+        const int rows0 = k0 + nb;
+        for (int cs = rows0; cs < ncols; cs += CH) {
+            const int cw = min(CH, ncols - cs);
+            {
+                // U12 = L11^{-1} A12 for this chunk, one column per thread, kept
+                // in the thread's own LDS column (also the GEMM's B operand).
+                const int col = cs + tid;
+                if (tid < cw) {
+                    T *cp = A + (size_t)col * ld + k0;
+                    for (int r = 0; r < NB; ++r) s_U[r][tid] = (r < nb) ? cp[r] : T(0);
+                    for (int r = 1; r < nb; ++r) {
+                        T s = s_U[r][tid];
+                        for (int q = 0; q < r; ++q) s -= s_L11[r][q] * s_U[q][tid];
+                        s_U[r][tid] = s;
+                    }
+                    for (int r = 0; r < nb; ++r) cp[r] = s_U[r][tid];
+                } else {
+                    for (int r = 0; r < NB; ++r) s_U[r][tid] = T(0);
+                }
+            }
+            __syncthreads();
+
+            const int mrows = n - rows0;
+            if (mrows > 0) {
+                const int nrt = (mrows + 15) >> 4;
+                const int nct = (cw + 15) >> 4;
+                const int i16 = lane & 15, k4 = lane >> 4;
+                for (int t = wave; t < nrt * nct; t += TPB / 64) {
+                    const int ct = t / nrt, rt = t - ct * nrt;
+                    const int r0 = rows0 + 16 * rt;
+                    const int cl = 16 * ct + i16;          // column within the chunk
+                    const bool cok = cl < cw;
+                    T *ccol = A + (size_t)(cs + cl) * ld + r0;
+                    typename Acc<T>::type acc;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[e] = cok ? ccol[Acc<T>::row(lane, e)] : T(0);
+                    const T *lcol = A + (size_t)k0 * ld + r0 + i16;
+#pragma unroll
+                    for (int kk = 0; kk < NB; kk += 4) {
+                        const int kx = kk + k4;
+                        const T a = (kx < nb) ? -lcol[(size_t)kx * ld] : T(0);
+                        const T bb = s_U[kx][cl < CH ? cl : 0];
+                        acc = mfma16(a, bb, acc);
+                    }
+                    if (cok) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) ccol[Acc<T>::row(lane, e)] = acc[e];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // ---- back substitution for the K right-hand sides ------------------
+    // The right-hand-side columns now hold L^{-1} P b; solve U x = that.
+    double *X = v.x + mt.x_off;
+    if (tid == 0) {
+        info_out[b] = info;
+        v.flag[b] = info;
+    }
+    if (info != 0) {
+        for (int i = tid; i < n * mt.K; i += TPB) X[i] = __builtin_nan("");
+        return;
+    }
+    T *y = &s_U[0][0];   // n <= PANEL_NMAX + 1 <= NB * CH values
+    for (int k = 0; k < mt.K; ++k) {
+        __syncthreads();
+        for (int i = tid; i < n; i += TPB) y[i] = A[(size_t)(n + k) * ld + i];
+        __syncthreads();
+        trsv_upper<T, T>(A, ld, n, y);
+        for (int i = tid; i < n; i += TPB) X[(size_t)k * n + i] = (double)y[i];
+    }
+}
+
+// Mixed precision: iterative refinement of X with the FP64 system in A64 and
+// the FP32 factors in A32.  One sweep: r = b - A x in FP64; stop if r is at
+// the FP64 backward-error floor, ||r||_inf <= sqrt(n) eps ||A||_inf ||x||_inf
+// (no further sweep can improve x); otherwise d = U^{-1} L^{-1} P r in FP32,
+// x += d, and stop once ||d||_inf <= tol ||x||_inf.
+__global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restrict__ info, double tol,
+                                                     int max_iter) {
+    const int b = blockIdx.x;
+    const AirfoilMeta mt = v.meta[b];
+    const int n = mt.n1, ld = mt.ld;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (info[b] != 0) {
+        if (tid == 0) {
+            v.iters[b] = 0;
+            v.flag[b] = info[b];
+        }
+        return;
+    }
+    const double *A = v.a64 + mt.a_off;
+    const float *LU = v.a32 + mt.a_off;
+    const int32_t *piv = v.piv + mt.piv_off;
+    double *X = v.x + mt.x_off;
+    __shared__ double sx[PANEL_NMAX + 1];
+    __shared__ double sr[PANEL_NMAX + 1];
+    __shared__ float sd[PANEL_NMAX + 1];
+    __shared__ int perm[PANEL_NMAX + 1];
+    __shared__ double red[3][TPB / 64];
+    if (tid == 0) {
+        for (int i = 0; i < n; ++i) perm[i] = i;
+        for (int i = 0; i < n; ++i) {
+            const int p = piv[i];
+            const int t0 = perm[i];
+            perm[i] = perm[p];
+            perm[p] = t0;
+        }
+    }
+    // block-wide max of three values (all threads receive the result)
+    auto bmax3 = [&](double &a0, double &a1, double &a2) {
+        for (int off = 32; off > 0; off >>= 1) {
+            a0 = fmax(a0, __shfl_xor(a0, off));
+            a1 = fmax(a1, __shfl_xor(a1, off));
+            a2 = fmax(a2, __shfl_xor(a2, off));
+        }
+        if (lane == 0) {
+            red[0][wave] = a0;
+            red[1][wave] = a1;
+            red[2][wave] = a2;
+        }
+        __syncthreads();
+        a0 = red[0][0];
+        a1 = red[1][0];
+        a2 = red[2][0];
+        for (int w = 1; w < TPB / 64; ++w) {
+            a0 = fmax(a0, red[0][w]);
+            a1 = fmax(a1, red[1][w]);
+            a2 = fmax(a2, red[2][w]);
+        }
+        __syncthreads();
+    };
+    const double floor_c = sqrt((double)n) * 2.220446049250313e-16;
+    double anrm = -1.0;   // ||A||_inf, found during the first residual
+    int worst = 0;
+    bool failed = max_iter == 0;
+    for (int k = 0; k < mt.K; ++k) {
+        for (int i = tid; i < n; i += TPB) sx[i] = X[(size_t)k * n + i];
+        __syncthreads();
+        bool conv = false;
+        int sweeps = 0;
+        for (int it = 0; it < max_iter && !conv; ++it) {
+            double rmax = 0.0, xmax = 0.0, rowmax = 0.0;
+            for (int i = tid; i < n; i += TPB) {
+                double s = A[(size_t)(n + k) * ld + i];
+                double ra = 0.0;
+                if (anrm < 0.0) {
+                    for (int j = 0; j < n; ++j) {
+                        const double a = A[(size_t)j * ld + i];
+                        s -= a * sx[j];
+                        ra += fabs(a);
+                    }
+                } else {
+                    for (int j = 0; j < n; ++j) s -= A[(size_t)j * ld + i] * sx[j];
+                }
+                sr[i] = s;
+                rmax = fmax(rmax, fabs(s));
+                xmax = fmax(xmax, fabs(sx[i]));
+                rowmax = fmax(rowmax, ra);
+            }
+            bmax3(rmax, xmax, rowmax);
+            if (anrm < 0.0) anrm = rowmax;
+            if (rmax <= floor_c * anrm * xmax) {
+                conv = true;
+                break;
+            }
+            for (int i = tid; i < n; i += TPB) sd[i] = (float)sr[perm[i]];
+            __syncthreads();
+            trsv_lower_unit<float, float>(LU, ld, n, sd);
+            trsv_upper<float, float>(LU, ld, n, sd);
+            double dmax = 0.0, xn = 0.0, unused = 0.0;
+            for (int i = tid; i < n; i += TPB) {
+                const double d = (double)sd[i];
+                const double x1 = sx[i] + d;
+                sx[i] = x1;
+                dmax = fmax(dmax, fabs(d));
+                xn = fmax(xn, fabs(x1));
+            }
+            bmax3(dmax, xn, unused);
+            ++sweeps;
+            conv = dmax <= tol * xn;
+        }
+        if (!conv) failed = true;
+        worst = max(worst, sweeps);
+        for (int i = tid; i < n; i += TPB) X[(size_t)k * n + i] = sx[i];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        v.iters[b] = worst;
+        if (failed) info[b] = -2;
+        v.flag[b] = info[b];
+    }
+}
+
+template <typename T, int NB, int R>
+void launch_lu(const WsView &v, int32_t B, int32_t *info, hipStream_t s) {
+    lu_kernel<T, NB, R><<<B, TPB, 0, s>>>(v, info);
+}
+
+template <typename T>
+hipError_t launch_lu_any(const WsView &v, int32_t B, int32_t max_n1, int32_t *info, hipStream_t s) {
+    const int R = (max_n1 + TPB - 1) / TPB;
+    if (R <= 1)
+        launch_lu<T, 32, 1>(v, B, info, s);
+    else if (R == 2)
+        launch_lu<T, 32, 2>(v, B, info, s);
+    else if (R == 3)
+        launch_lu<T, 16, 3>(v, B, info, s);
+    else
+        launch_lu<T, 16, 5>(v, B, info, s);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_factor_solve(const WsView &v, int32_t B, int32_t max_n1, int32_t mixed, double tol,
+                               int32_t max_iter, int32_t *info, hipStream_t stream) {
+    hipError_t e;
+    if (!mixed) {
+        e = launch_lu_any<double>(v, B, max_n1, info, stream);
+    } else {
+        e = launch_lu_any<float>(v, B, max_n1, info, stream);
+        if (e != hipSuccess) return e;
+        refine_kernel<<<B, TPB, 0, stream>>>(v, info, tol, max_iter);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace panel

@@ -1,0 +1,289 @@
+// panel_abi.cpp -- host side of the C ABI declared in include/panel.h:
+// argument validation (before any HIP call), plan metadata, workspace layout
+// and kernel launches.  No device memory is allocated here.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "panel_internal.hpp"
+
+using namespace panel;
+
+struct panel_plan {
+    int32_t B = 0;
+    int32_t precision = 0;
+    int32_t max_n1 = 0;
+    int32_t max_k = 0;
+    int32_t max_cols = 0;  // max over airfoils of n1 + K
+    std::vector<int32_t> node_off, alpha_off;
+    std::vector<char> blob;  // header | meta | order, copied by workspace_init
+    WsLayout layout{};
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+panel_status fail(panel_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+panel_status ok() {
+    g_last_error.clear();
+    return PANEL_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+panel_status check_hip(hipError_t e, const char *what) {
+    if (e != hipSuccess)
+        return fail(PANEL_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *panel_status_str(int32_t s) {
+    switch (s) {
+        case PANEL_OK: return "PANEL_OK";
+        case PANEL_EINVAL: return "PANEL_EINVAL: invalid argument";
+        case PANEL_ENOMEM: return "PANEL_ENOMEM: host allocation failed";
+        case PANEL_EHIP: return "PANEL_EHIP: HIP runtime error";
+        case PANEL_EUNSUPPORTED: return "PANEL_EUNSUPPORTED: unsupported request";
+        default: return "unknown panel_status";
+    }
+}
+
+const char *panel_last_error(void) { return g_last_error.c_str(); }
+
+panel_status panel_plan_create(int32_t B, const int32_t *h_node_offsets,
+                               const int32_t *h_alpha_offsets, int32_t precision,
+                               panel_plan **out) {
+    if (!out) return fail(PANEL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (B < 1) return fail(PANEL_EINVAL, "B must be >= 1");
+    if (!h_node_offsets || !h_alpha_offsets) return fail(PANEL_EINVAL, "offset array is NULL");
+    if (precision != PANEL_FP64 && precision != PANEL_FP32_REFINE)
+        return fail(PANEL_EINVAL, "unknown precision");
+    if (h_node_offsets[0] != 0 || h_alpha_offsets[0] != 0)
+        return fail(PANEL_EINVAL, "offsets must start at 0");
+    for (int32_t b = 0; b < B; ++b) {
+        int64_t n = int64_t(h_node_offsets[b + 1]) - h_node_offsets[b];
+        int64_t k = int64_t(h_alpha_offsets[b + 1]) - h_alpha_offsets[b];
+        if (n - 1 < PANEL_NMIN || n - 1 > PANEL_NMAX) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "airfoil %d has %lld panels (allowed %d..%d)", b,
+                          (long long)(n - 1), PANEL_NMIN, PANEL_NMAX);
+            return fail(PANEL_EINVAL, buf);
+        }
+        if (k < 1 || k > PANEL_KMAX) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "airfoil %d has %lld angles (allowed 1..%d)", b,
+                          (long long)k, PANEL_KMAX);
+            return fail(PANEL_EINVAL, buf);
+        }
+    }
+    panel_plan *p = new (std::nothrow) panel_plan;
+    if (!p) return fail(PANEL_ENOMEM, "plan allocation");
+    try {
+        p->B = B;
+        p->precision = precision;
+        p->node_off.assign(h_node_offsets, h_node_offsets + B + 1);
+        p->alpha_off.assign(h_alpha_offsets, h_alpha_offsets + B + 1);
+        std::vector<AirfoilMeta> meta(B);
+        int64_t a_off = 0, x_off = 0, s_off = 0, piv_off = 0;
+        std::vector<double> cost(B);
+        for (int32_t b = 0; b < B; ++b) {
+            AirfoilMeta &m = meta[b];
+            m.N = h_node_offsets[b + 1] - h_node_offsets[b] - 1;
+            m.K = h_alpha_offsets[b + 1] - h_alpha_offsets[b];
+            m.n1 = m.N + 1;
+            m.ld = (m.n1 + 15) & ~15;
+            m.node_off = h_node_offsets[b];
+            m.alpha_off = h_alpha_offsets[b];
+            m.panel_off = h_node_offsets[b] - b;
+            m.a_off = a_off;
+            m.x_off = x_off;
+            m.s_off = s_off;
+            m.piv_off = int32_t(piv_off);
+            // keep every system 128-byte aligned in both precisions
+            a_off += (int64_t(m.ld) * (m.n1 + m.K) + 31) & ~int64_t(31);
+            x_off += int64_t(m.n1) * m.K;
+            s_off += int64_t(m.N) * m.K;
+            piv_off += m.n1;
+            p->max_n1 = std::max(p->max_n1, m.n1);
+            p->max_k = std::max(p->max_k, m.K);
+            p->max_cols = std::max(p->max_cols, m.n1 + m.K);
+            double n = m.n1;
+            cost[b] = n * n * n / 1.5 + 2.0 * n * n * m.K;
+        }
+        // Longest-processing-time order: the most expensive airfoils first.
+        std::vector<int32_t> order(B);
+        for (int32_t b = 0; b < B; ++b) order[b] = b;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t c) { return cost[a] > cost[c]; });
+
+        WsLayout &l = p->layout;
+        size_t off = align256(sizeof(WsHeader));
+        l.meta = off;
+        off = align256(off + sizeof(AirfoilMeta) * B);
+        l.order = off;
+        off = align256(off + sizeof(int32_t) * B);
+        l.flag = off;
+        off = align256(off + sizeof(int32_t) * B);
+        l.chord = off;
+        off = align256(off + sizeof(double) * B);
+        l.alpha = off;
+        off = align256(off + sizeof(double) * h_alpha_offsets[B]);
+        l.geom = off;
+        off = align256(off + sizeof(PanelGeom) * (size_t(h_node_offsets[B]) - B));
+        l.a64 = off;
+        off = align256(off + sizeof(double) * size_t(a_off));
+        if (precision == PANEL_FP32_REFINE) {
+            l.a32 = off;
+            off = align256(off + sizeof(float) * size_t(a_off));
+        } else {
+            l.a32 = 0;
+        }
+        l.x = off;
+        off = align256(off + sizeof(double) * size_t(x_off));
+        l.piv = off;
+        off = align256(off + sizeof(int32_t) * size_t(piv_off));
+        l.iters = off;
+        off = align256(off + sizeof(int32_t) * B);
+        l.total = off;
+
+        WsHeader hdr{};
+        hdr.vinf = 1.0;
+        hdr.B = B;
+        hdr.precision = precision;
+        hdr.max_n1 = p->max_n1;
+        p->blob.assign(l.flag, 0);
+        std::memcpy(p->blob.data(), &hdr, sizeof hdr);
+        std::memcpy(p->blob.data() + l.meta, meta.data(), sizeof(AirfoilMeta) * B);
+        std::memcpy(p->blob.data() + l.order, order.data(), sizeof(int32_t) * B);
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return fail(PANEL_ENOMEM, "plan metadata allocation");
+    }
+    *out = p;
+    return ok();
+}
+
+void panel_plan_destroy(panel_plan *plan) { delete plan; }
+
+panel_status panel_workspace_layout(const panel_plan *plan, int32_t b, int64_t *h_desc) {
+    if (!plan || !h_desc) return fail(PANEL_EINVAL, "NULL argument");
+    if (b < 0 || b >= plan->B) return fail(PANEL_EINVAL, "airfoil index out of range");
+    AirfoilMeta m;
+    std::memcpy(&m, plan->blob.data() + plan->layout.meta + sizeof(AirfoilMeta) * b, sizeof m);
+    const WsLayout &l = plan->layout;
+    h_desc[0] = int64_t(l.a64 + sizeof(double) * m.a_off);
+    h_desc[1] = l.a32 ? int64_t(l.a32 + sizeof(float) * m.a_off) : -1;
+    h_desc[2] = int64_t(l.x + sizeof(double) * m.x_off);
+    h_desc[3] = int64_t(l.piv + sizeof(int32_t) * m.piv_off);
+    h_desc[4] = m.n1;
+    h_desc[5] = m.ld;
+    h_desc[6] = m.K;
+    h_desc[7] = int64_t(l.iters + sizeof(int32_t) * b);
+    return ok();
+}
+
+panel_status panel_workspace_size(const panel_plan *plan, size_t *bytes) {
+    if (!plan || !bytes) return fail(PANEL_EINVAL, "NULL argument");
+    *bytes = plan->layout.total;
+    return ok();
+}
+
+panel_status panel_workspace_init(const panel_plan *plan, void *ws, void *stream) {
+    if (!plan || !ws) return fail(PANEL_EINVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(PANEL_EINVAL, "workspace must be 256-byte aligned");
+    hipError_t e = hipMemcpyAsync(ws, plan->blob.data(), plan->blob.size(), hipMemcpyHostToDevice,
+                                  static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return check_hip(e, "workspace metadata copy");
+    // The source is pageable host memory owned by the plan; make the copy
+    // complete before returning so the plan may be destroyed at any time.
+    e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    return check_hip(e, "workspace metadata copy");
+}
+
+panel_status panel_assemble(const panel_plan *plan, const double *xy, const double *alpha,
+                            const double *chord, double vinf, void *ws, void *stream) {
+    if (!plan || !xy || !alpha || !ws) return fail(PANEL_EINVAL, "NULL argument");
+    if (!aligned8(xy) || !aligned8(alpha) || (chord && !aligned8(chord)))
+        return fail(PANEL_EINVAL, "arrays must be 8-byte aligned");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(PANEL_EINVAL, "workspace must be 256-byte aligned");
+    if (!(std::isfinite(vinf) && vinf > 0.0)) return fail(PANEL_EINVAL, "vinf must be finite and > 0");
+    WsView v = ws_view(ws, plan->layout);
+    hipError_t e = launch_assemble(v, plan->B, plan->max_cols, plan->precision == PANEL_FP32_REFINE,
+                                   xy, alpha, chord, vinf, static_cast<hipStream_t>(stream));
+    return check_hip(e, "assembly launch");
+}
+
+panel_status panel_factor_solve(const panel_plan *plan, void *ws, double refine_tol,
+                                int32_t max_iter, int32_t *info, void *stream) {
+    if (!plan || !ws || !info) return fail(PANEL_EINVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(PANEL_EINVAL, "workspace must be 256-byte aligned");
+    const bool mixed = plan->precision == PANEL_FP32_REFINE;
+    if (mixed) {
+        if (!(std::isfinite(refine_tol) && refine_tol > 0.0))
+            return fail(PANEL_EINVAL, "refine_tol must be finite and > 0");
+        if (max_iter < 0 || max_iter > 100) return fail(PANEL_EINVAL, "max_iter must be in 0..100");
+    }
+    WsView v = ws_view(ws, plan->layout);
+    hipError_t e = launch_factor_solve(v, plan->B, plan->max_n1, mixed, refine_tol, max_iter, info,
+                                       static_cast<hipStream_t>(stream));
+    return check_hip(e, "factor/solve launch");
+}
+
+panel_status panel_forces(const panel_plan *plan, const void *ws, double *gamma, double *cp,
+                          double *cl, double *cl_p, void *stream) {
+    if (!plan || !ws || !cl) return fail(PANEL_EINVAL, "NULL argument");
+    if ((gamma && !aligned8(gamma)) || (cp && !aligned8(cp)) || !aligned8(cl) || (cl_p && !aligned8(cl_p)))
+        return fail(PANEL_EINVAL, "arrays must be 8-byte aligned");
+    WsView v = ws_view(const_cast<void *>(ws), plan->layout);
+    hipError_t e = launch_forces(v, plan->B, plan->max_k, gamma, cp, cl, cl_p,
+                                 static_cast<hipStream_t>(stream));
+    return check_hip(e, "forces launch");
+}
+
+panel_status panel_adjoint(const panel_plan *plan, const void *ws, const double *xy,
+                           const double *dcl, double *dxy, void *stream) {
+    if (!plan || !ws || !xy || !dcl || !dxy) return fail(PANEL_EINVAL, "NULL argument");
+    if (!aligned8(xy) || !aligned8(dcl) || !aligned8(dxy))
+        return fail(PANEL_EINVAL, "arrays must be 8-byte aligned");
+    WsView v = ws_view(const_cast<void *>(ws), plan->layout);
+    hipError_t e = launch_adjoint(v, plan->B, plan->max_n1, plan->precision == PANEL_FP32_REFINE, xy,
+                                  dcl, dxy, static_cast<hipStream_t>(stream));
+    return check_hip(e, "adjoint launch");
+}
+
+panel_status panel_naca4(int32_t B, const int32_t *node_off, int32_t closed_te, const double *mpt,
+                         double *xy, void *stream) {
+    if (B < 1) return fail(PANEL_EINVAL, "B must be >= 1");
+    if (!node_off || !mpt || !xy) return fail(PANEL_EINVAL, "NULL argument");
+    if (!aligned8(mpt) || !aligned8(xy)) return fail(PANEL_EINVAL, "arrays must be 8-byte aligned");
+    hipError_t e = launch_naca4(B, node_off, closed_te, mpt, xy, static_cast<hipStream_t>(stream));
+    return check_hip(e, "naca4 launch");
+}
+
+panel_status panel_naca4_vjp(int32_t B, const int32_t *node_off, int32_t closed_te,
+                             const double *mpt, const double *dxy, double *dmpt, void *stream) {
+    if (B < 1) return fail(PANEL_EINVAL, "B must be >= 1");
+    if (!node_off || !mpt || !dxy || !dmpt) return fail(PANEL_EINVAL, "NULL argument");
+    if (!aligned8(mpt) || !aligned8(dxy) || !aligned8(dmpt))
+        return fail(PANEL_EINVAL, "arrays must be 8-byte aligned");
+    hipError_t e = launch_naca4_vjp(B, node_off, closed_te, mpt, dxy, dmpt, static_cast<hipStream_t>(stream));
+    return check_hip(e, "naca4 vjp launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// panel_internal.hpp -- workspace layout and kernel entry declarations shared
+// by the host library and the gfx950 kernels of the batched panel method.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/panel.h"
+
+namespace panel {
+
+// Per-airfoil record, written once by panel_workspace_init.
+struct AirfoilMeta {
+    int64_t a_off;      // element offset of the augmented system [M | rhs]
+                        // (ld rows x (n1 + K) columns, column-major) in A64
+                        // and, for the mixed path, in A32
+    int64_t x_off;      // element offset of the K solutions (n1 each) in X
+    int64_t s_off;      // offset of gamma / cp outputs: sum N_b' K_b'
+    int32_t N;          // panels
+    int32_t K;          // angles of attack
+    int32_t n1;         // system order N + 1
+    int32_t ld;         // leading dimension (n1 rounded up to 16)
+    int32_t node_off;   // first node of the airfoil in xy
+    int32_t alpha_off;  // first angle in alpha / cl
+    int32_t panel_off;  // first panel in the geometry cache (node_off - b)
+    int32_t piv_off;    // first pivot (sum n1_b')
+};
+static_assert(sizeof(AirfoilMeta) == 56, "meta layout");
+
+// Geometry cached by the assembly for the forces / adjoint steps.
+struct PanelGeom {
+    double L, tx, ty, pad;
+};
+
+// Byte offsets of the workspace sections (all 256-byte aligned).
+struct WsLayout {
+    size_t meta, order, flag, chord, alpha, geom, a64, a32, x, piv, iters, total;
+};
+
+// Scalars copied with the metadata.
+struct WsHeader {
+    double vinf;
+    int32_t B;
+    int32_t precision;
+    int32_t max_n1;
+    int32_t pad;
+};
+
+// Device view of a workspace.
+struct WsView {
+    WsHeader *hdr;
+    AirfoilMeta *meta;
+    int32_t *order;     // airfoils by decreasing cost (LPT order)
+    int32_t *flag;      // per airfoil: 0 ok, -1 bad geometry (set by assembly)
+    double *chord;      // per airfoil
+    double *alpha;      // per angle
+    PanelGeom *geom;    // per panel
+    double *a64;        // FP64 systems (factored in place for PANEL_FP64)
+    float *a32;         // FP32 systems (mixed path; factored in place)
+    double *x;          // solutions
+    int32_t *piv;       // pivots (0-based row exchanged at each step)
+    int32_t *iters;     // refinement sweeps per airfoil
+};
+
+inline __host__ __device__ WsView ws_view(void *ws, const WsLayout &l) {
+    char *b = static_cast<char *>(ws);
+    WsView v;
+    v.hdr = reinterpret_cast<WsHeader *>(b);
+    v.meta = reinterpret_cast<AirfoilMeta *>(b + l.meta);
+    v.order = reinterpret_cast<int32_t *>(b + l.order);
+    v.flag = reinterpret_cast<int32_t *>(b + l.flag);
+    v.chord = reinterpret_cast<double *>(b + l.chord);
+    v.alpha = reinterpret_cast<double *>(b + l.alpha);
+    v.geom = reinterpret_cast<PanelGeom *>(b + l.geom);
+    v.a64 = reinterpret_cast<double *>(b + l.a64);
+    v.a32 = l.a32 ? reinterpret_cast<float *>(b + l.a32) : nullptr;
+    v.x = reinterpret_cast<double *>(b + l.x);
+    v.piv = reinterpret_cast<int32_t *>(b + l.piv);
+    v.iters = reinterpret_cast<int32_t *>(b + l.iters);
+    return v;
+}
+
+// Kernel launchers (each enqueues on `stream`, returns hipGetLastError()).
+hipError_t launch_naca4(int32_t B, const int32_t *node_off, int32_t closed_te, const double *mpt,
+                        double *xy, hipStream_t stream);
+hipError_t launch_naca4_vjp(int32_t B, const int32_t *node_off, int32_t closed_te,
+                            const double *mpt, const double *dxy, double *dmpt, hipStream_t stream);
+hipError_t launch_assemble(const WsView &v, int32_t B, int32_t max_cols, int32_t mixed,
+                           const double *xy, const double *alpha, const double *chord, double vinf,
+                           hipStream_t stream);
+hipError_t launch_factor_solve(const WsView &v, int32_t B, int32_t max_n1, int32_t mixed,
+                               double tol, int32_t max_iter, int32_t *info, hipStream_t stream);
+hipError_t launch_forces(const WsView &v, int32_t B, int32_t max_k, double *gamma, double *cp,
+                         double *cl, double *cl_p, hipStream_t stream);
+hipError_t launch_adjoint(const WsView &v, int32_t B, int32_t max_n1, int32_t mixed,
+                          const double *xy, const double *dcl, double *dxy, hipStream_t stream);
+
+}  // namespace panel

@@ -1,0 +1,149 @@
+"""Convenience layer over the C ABI: a batch solver object and autograd hooks.
+
+torch provides the device memory (workspace and outputs) and the stream;
+all arithmetic happens in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _binding as B
+
+
+def _aligned_workspace(nbytes: int, device) -> tuple[torch.Tensor, torch.Tensor]:
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % 256
+    return raw, raw[off:off + nbytes]
+
+
+class PanelSolver:
+    """One batch layout (node and angle offsets) with its workspace and outputs.
+
+    Typical use (all tensors on the GPU, float64)::
+
+        s = PanelSolver(node_offsets, alpha_offsets)
+        out = s.solve(xy, alpha)          # dict of gamma, cp, cl, cl_p, info
+    """
+
+    def __init__(self, node_offsets, alpha_offsets, precision=B.PANEL_FP64, device="cuda"):
+        self.device = torch.device(device)
+        self.plan = B.Plan(node_offsets, alpha_offsets, precision)
+        self.precision = int(precision)
+        p = self.plan
+        self._ws_raw, self.ws = _aligned_workspace(p.workspace_size(), self.device)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.info = torch.zeros(p.B, dtype=torch.int32, device=self.device)
+        self.cl = torch.empty(p.n_alpha, **f64)
+        self.cl_p = torch.empty(p.n_alpha, **f64)
+        self.gamma = torch.empty(p.n_out, **f64)
+        self.cp = torch.empty(p.n_out, **f64)
+        self.node_off_dev = torch.as_tensor(p.node_offsets, dtype=torch.int32, device=self.device)
+        B.panel_workspace_init(p, self.ws)
+
+    @property
+    def B(self) -> int:
+        return self.plan.B
+
+    # -- steps ---------------------------------------------------------------
+    def naca4(self, mpt: torch.Tensor, closed_te: bool = True, out: torch.Tensor | None = None):
+        xy = out if out is not None else torch.empty(2 * self.plan.n_nodes, dtype=torch.float64,
+                                                     device=self.device)
+        B.panel_naca4(self.plan.B, self.node_off_dev, closed_te, mpt, xy)
+        return xy
+
+    def assemble(self, xy, alpha, chord=None, vinf=1.0):
+        B.panel_assemble(self.plan, xy, alpha, chord, vinf, self.ws)
+
+    def factor_solve(self, refine_tol=1e-10, max_iter=10):
+        B.panel_factor_solve(self.plan, self.ws, refine_tol, max_iter, self.info)
+
+    def forces(self, fields=True):
+        B.panel_forces(self.plan, self.ws, self.gamma if fields else None, self.cp if fields else None,
+                       self.cl, self.cl_p)
+
+    def step(self, xy, alpha, chord=None, vinf=1.0, refine_tol=1e-10, max_iter=10, fields=True):
+        """assemble -> factor_solve -> forces, enqueued on the current stream."""
+        self.assemble(xy, alpha, chord, vinf)
+        self.factor_solve(refine_tol, max_iter)
+        self.forces(fields)
+
+    def solve(self, xy, alpha, chord=None, vinf=1.0, refine_tol=1e-10, max_iter=10):
+        self.step(xy, alpha, chord, vinf, refine_tol, max_iter)
+        return dict(gamma=self.gamma, cp=self.cp, cl=self.cl, cl_p=self.cl_p, info=self.info)
+
+    def adjoint(self, xy, dcl, out=None):
+        dxy = out if out is not None else torch.empty(2 * self.plan.n_nodes, dtype=torch.float64,
+                                                      device=self.device)
+        B.panel_adjoint(self.plan, self.ws, xy, dcl, dxy)
+        return dxy
+
+    def naca4_vjp(self, mpt, dxy, closed_te=True):
+        dmpt = torch.empty_like(mpt)
+        B.panel_naca4_vjp(self.plan.B, self.node_off_dev, closed_te, mpt, dxy, dmpt)
+        return dmpt
+
+    # -- inspection ------------------------------------------------------------
+    def system(self, b: int, which: str = "a64") -> tuple[np.ndarray, np.ndarray]:
+        """Airfoil b's stored system: (matrix n1 x n1, right-hand sides K x n1).
+
+        After panel_assemble this is M and b; after panel_factor_solve the
+        factored copy holds L\\U and L^{-1} P b."""
+        d = self.plan.layout(b)
+        n1, ld, K = d["n1"], d["ld"], d["K"]
+        if which == "a64":
+            t = self.ws[d["a64"]:d["a64"] + 8 * ld * (n1 + K)].view(torch.float64)
+        else:
+            t = self.ws[d["a32"]:d["a32"] + 4 * ld * (n1 + K)].view(torch.float32)
+        cols = t.cpu().numpy().reshape(n1 + K, ld)[:, :n1]
+        return cols[:n1].T.copy(), cols[n1:].copy()
+
+    def pivots(self, b: int) -> np.ndarray:
+        d = self.plan.layout(b)
+        return self.ws[d["piv"]:d["piv"] + 4 * d["n1"]].view(torch.int32).cpu().numpy()
+
+    def refine_iterations(self) -> np.ndarray:
+        """Refinement sweeps per airfoil of the last mixed-precision solve."""
+        d = self.plan.layout(0)
+        return self.ws[d["iters"]:d["iters"] + 4 * self.plan.B].view(torch.int32).cpu().numpy()
+
+
+class _ClFunction(torch.autograd.Function):
+    """Cl(xy) with the hand-written adjoint kernel as its backward."""
+
+    @staticmethod
+    def forward(ctx, xy, alpha, solver: PanelSolver, chord, vinf):
+        solver.step(xy, alpha, chord, vinf, fields=False)
+        ctx.solver = solver
+        ctx.save_for_backward(xy)
+        return solver.cl.clone()
+
+    @staticmethod
+    def backward(ctx, dcl):
+        (xy,) = ctx.saved_tensors
+        dxy = ctx.solver.adjoint(xy, dcl.contiguous())
+        return dxy, None, None, None, None
+
+
+def panel_cl(xy, alpha, solver: PanelSolver, chord=None, vinf=1.0):
+    """Lift coefficients of a batch, differentiable with respect to the nodes."""
+    return _ClFunction.apply(xy, alpha, solver, chord, vinf)
+
+
+class _NacaFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, mpt, solver: PanelSolver, closed_te):
+        ctx.solver, ctx.closed_te = solver, closed_te
+        ctx.save_for_backward(mpt)
+        return solver.naca4(mpt, closed_te)
+
+    @staticmethod
+    def backward(ctx, dxy):
+        (mpt,) = ctx.saved_tensors
+        return ctx.solver.naca4_vjp(mpt, dxy.contiguous(), ctx.closed_te), None, None
+
+
+def naca_cl(mpt, alpha, solver: PanelSolver, closed_te=True, vinf=1.0):
+    """Cl of NACA sections, differentiable with respect to (m, p, t)."""
+    xy = _NacaFunction.apply(mpt, solver, closed_te)
+    return panel_cl(xy, alpha, solver, None, vinf)

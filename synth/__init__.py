@@ -163,3 +163,16 @@ def pack_nodes(node_lists) -> tuple[np.ndarray, np.ndarray]:
     off[1:] = np.cumsum([len(x) for x in node_lists])
     xy = np.concatenate([np.asarray(x, dtype=np.float64).reshape(-1, 2) for x in node_lists])
     return np.ascontiguousarray(xy.reshape(-1)), off
+
+
+def joukowski_batch(seed: int, B: int, n_panels) -> tuple[np.ndarray, np.ndarray]:
+    """B cambered Joukowski sections with seeded circle centres (airfoil-like,
+    cusped trailing edge), packed as (xy_flat, node_offsets).  ``n_panels`` is
+    an int or a sequence of B even ints."""
+    rng = np.random.default_rng(seed)
+    ns = np.broadcast_to(np.asarray(n_panels), (B,))
+    nodes = []
+    for b in range(B):
+        mu = complex(-rng.uniform(0.01, 0.06), rng.uniform(0.0, 0.06))
+        nodes.append(joukowski_nodes(int(ns[b]), 0.25, mu))
+    return pack_nodes(nodes)
