@@ -1,12 +1,389 @@
-// adjoint.hip -- reverse-mode lift sensitivity (placeholder until the
-// transposed-solve kernels land).
+// adjoint.hip -- reverse-mode sensitivity of the lift to the node coordinates
+// on gfx950 (the paper optimises airfoil shapes, Sec. 2; this gives the
+// shape gradient of the Kutta-Joukowski lift of its panel system).
+//
+// For one airfoil with solutions x_k of M x_k = r_k (angles k < K) and lift
+// Cl_k = -2 sum_i x_k,i L_i / (vinf c), the cotangents dcl_k give
+//   xbar   = sum_k dcl_k x_k
+//   lambda = M^{-T} w,   w_i = -2 L_i / (vinf c) (i < N),  w_N = 0
+//   dP     = -2/(vinf c) sum_i xbar_i dL_i/dP                 (explicit)
+//          + sum_j lambda_j sum_k dcl_k dr_k,j/dP              (right-hand side)
+//          - sum_{j,i} lambda_j xbar_i dG_ji/dP                (matrix)
+// One transposed solve serves all K angles.  It reuses the factors left by
+// the forward solve (FP64, or FP32 factors with FP64 refinement of the
+// transposed system).  The matrix term re-evaluates closed-form derivatives
+// of the panel integral G_ji(m, A, B) (control point m = m_j, panel i from A
+// to B, unit tangent t, normal n = (t_y, -t_x), xi = (m-A).t, eta = (m-A).n,
+// l1 = log|m-A|^2, l2 = log|m-B|^2, th = angle subtended by the panel):
+//   dG/dm = -(1/2pi) [ (l1-l2)/2 t - th n ]
+//   dG/dB = I/(2 pi L) + (G/L) t,
+//     I = (xi (l1-l2)/2 - L - eta th) t + (-xi th - eta (l1-l2)/2) n
+//   dG/dA = -dG/dm - dG/dB                  (translation invariance)
+// and, on the diagonal, G_ii = (L/2pi)(1 - log(L/2)), dG_ii/dL = -log(L/2)/2pi.
+// Pass 1 (one thread per control point) sums the m-derivatives, pass 2 (one
+// thread per panel) the endpoint derivatives; no cross-thread reductions.
+#include <climits>
+
 #include "panel_internal.hpp"
+#include "wave.hpp"
 
 namespace panel {
+namespace {
 
-hipError_t launch_adjoint(const WsView &, int32_t, int32_t, int32_t, const double *, const double *,
-                          double *, hipStream_t) {
-    return hipErrorNotSupported;
+constexpr int TPB = 256;
+constexpr int SB = 64;
+constexpr double kInv2Pi = 0.15915494309189535;
+constexpr double kInv4Pi = 0.07957747154594767;
+
+template <typename T> __device__ inline const T *factors(const WsView &v, const AirfoilMeta &mt);
+template <> __device__ inline const double *factors<double>(const WsView &v, const AirfoilMeta &mt) {
+    return v.a64 + mt.a_off;
+}
+template <> __device__ inline const float *factors<float>(const WsView &v, const AirfoilMeta &mt) {
+    return v.a32 + mt.a_off;
+}
+
+// Solve U^T z = y in place (U upper, column-major); y in LDS, V accumulation type.
+template <typename T, typename V>
+__device__ void trsv_upper_t(const T *U, int ld, int n, V *y, T *sblk, V *part) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nblk = (n + SB - 1) / SB;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int rb = blk * SB, w = min(SB, n - rb);
+        // y_i -= sum_{j < rb} U[j][i] y_j for the block's rows: four partial
+        // sums per row (one per wavefront), each over a quarter of j
+        {
+            const int i = rb + lane;
+            V s = V(0);
+            if (lane < w) {
+                const T *col = U + (size_t)i * ld;
+                for (int j = wave; j < rb; j += TPB / 64) s += V(col[j]) * y[j];
+            }
+            part[wave * SB + lane] = s;
+        }
+        for (int idx = tid; idx < SB * SB; idx += TPB) {
+            const int c = idx >> 6, r = idx & 63;
+            sblk[idx] = (c < w && r <= c) ? U[(size_t)(rb + c) * ld + rb + r] : T(0);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            V yi = V(0), dinv = V(0);
+            if (lane < w) {
+                yi = y[rb + lane] - ((part[lane] + part[SB + lane]) + (part[2 * SB + lane] + part[3 * SB + lane]));
+                dinv = V(1) / V(sblk[lane * SB + lane]);
+            }
+            for (int j = 0; j < w; ++j) {
+                if (lane == j) yi *= dinv;
+                const V zj = readlane_t(yi, j);
+                if (lane > j && lane < w) yi -= V(sblk[lane * SB + j]) * zj;
+            }
+            if (lane < w) y[rb + lane] = yi;
+        }
+        __syncthreads();
+    }
+}
+
+// Solve L^T y = z in place (L unit lower, column-major); y in LDS.
+template <typename T, typename V>
+__device__ void trsv_lower_unit_t(const T *L, int ld, int n, V *y, T *sblk, V *part) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nblk = (n + SB - 1) / SB;
+    for (int blk = nblk - 1; blk >= 0; --blk) {
+        const int rb = blk * SB, w = min(SB, n - rb), re = rb + w;
+        {
+            const int i = rb + lane;
+            V s = V(0);
+            if (lane < w) {
+                const T *col = L + (size_t)i * ld;
+                for (int j = re + wave; j < n; j += TPB / 64) s += V(col[j]) * y[j];
+            }
+            part[wave * SB + lane] = s;
+        }
+        for (int idx = tid; idx < SB * SB; idx += TPB) {
+            const int c = idx >> 6, r = idx & 63;
+            sblk[idx] = (c < w && r < w && r > c) ? L[(size_t)(rb + c) * ld + rb + r] : T(0);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            V yi = V(0);
+            if (lane < w)
+                yi = y[rb + lane] - ((part[lane] + part[SB + lane]) + (part[2 * SB + lane] + part[3 * SB + lane]));
+            for (int j = w - 1; j >= 0; --j) {
+                const V yj = readlane_t(yi, j);
+                if (lane < j) yi -= V(sblk[lane * SB + j]) * yj;
+            }
+            if (lane < w) y[rb + lane] = yi;
+        }
+        __syncthreads();
+    }
+}
+
+// lambda = (P^T L U)^{-T} w = P^T L^{-T} U^{-T} w with the stored factors.
+template <typename T, typename V>
+__device__ void solve_transposed(const T *LU, int ld, int n, const int *perm, V *y, V *tmp, T *sblk,
+                                 V *part) {
+    trsv_upper_t<T, V>(LU, ld, n, y, sblk, part);
+    trsv_lower_unit_t<T, V>(LU, ld, n, y, sblk, part);
+    // undo the row permutation: (P^T y)[perm[i]] = y[i]
+    for (int i = threadIdx.x; i < n; i += TPB) tmp[perm[i]] = y[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += TPB) y[i] = tmp[i];
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__restrict__ xy,
+                                                      const double *__restrict__ dcl,
+                                                      double *__restrict__ dxy) {
+    const int b = blockIdx.x;
+    const AirfoilMeta mt = v.meta[b];
+    const int N = mt.N, n1 = mt.n1, K = mt.K, ld = mt.ld;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *out = dxy + 2 * (size_t)mt.node_off;
+    if (v.flag[b] != 0) {
+        for (int k = tid; k < 2 * (N + 1); k += TPB) out[k] = __builtin_nan("");
+        return;
+    }
+    __shared__ double sx[PANEL_NMAX + 1], sy[PANEL_NMAX + 1];
+    __shared__ double xbar[PANEL_NMAX + 1], lam[PANEL_NMAX + 1];
+    __shared__ double tmp[PANEL_NMAX + 1];
+    __shared__ double gmx[PANEL_NMAX], gmy[PANEL_NMAX];
+    __shared__ int perm[PANEL_NMAX + 1];
+    __shared__ T sblk[SB * SB];
+    __shared__ double part[(TPB / 64) * SB];
+    __shared__ double red[2][TPB / 64];
+
+    const double *P = xy + 2 * (size_t)mt.node_off;
+    for (int k = tid; k <= N; k += TPB) {
+        sx[k] = P[2 * k];
+        sy[k] = P[2 * k + 1];
+    }
+    const double vinf = v.hdr->vinf, chord = v.chord[b];
+    const double *X = v.x + mt.x_off;
+    double S = 0.0, Cc = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double a = v.alpha[mt.alpha_off + k], d = dcl[mt.alpha_off + k];
+        S += d * sin(a);
+        Cc += d * cos(a);
+    }
+    for (int i = tid; i < n1; i += TPB) {
+        double s = 0.0;
+        for (int k = 0; k < K; ++k) s += dcl[mt.alpha_off + k] * X[(size_t)k * n1 + i];
+        xbar[i] = s;
+    }
+    if (tid == 0) {
+        const int32_t *piv = v.piv + mt.piv_off;
+        for (int i = 0; i < n1; ++i) perm[i] = i;
+        for (int i = 0; i < n1; ++i) {
+            const int p = piv[i];
+            const int t0 = perm[i];
+            perm[i] = perm[p];
+            perm[p] = t0;
+        }
+    }
+    __syncthreads();
+    const double wscale = -2.0 / (vinf * chord);
+    for (int i = tid; i < n1; i += TPB) {
+        double w = 0.0;
+        if (i < N) {
+            const double hx = sx[i + 1] - sx[i], hy = sy[i + 1] - sy[i];
+            w = wscale * sqrt(hx * hx + hy * hy);
+        }
+        tmp[i] = w;
+    }
+    __syncthreads();
+
+    const T *LU = factors<T>(v, mt);
+    if constexpr (sizeof(T) == 8) {
+        for (int i = tid; i < n1; i += TPB) lam[i] = tmp[i];
+        __syncthreads();
+        solve_transposed<double, double>(LU, ld, n1, perm, lam, tmp, sblk, part);
+    } else {
+        // FP32 factors: lambda from U^T/L^T in FP32, then FP64 refinement of
+        // the transposed system against the FP64 matrix in A64.
+        const double *A = v.a64 + mt.a_off;
+        __shared__ double wv[PANEL_NMAX + 1];
+        __shared__ float ylo[PANEL_NMAX + 1], tlo[PANEL_NMAX + 1];
+        __shared__ float partf[(TPB / 64) * SB];
+        for (int i = tid; i < n1; i += TPB) {
+            wv[i] = tmp[i];
+            ylo[i] = (float)tmp[i];
+        }
+        __syncthreads();
+        solve_transposed<float, float>(LU, ld, n1, perm, ylo, tlo, sblk, partf);
+        for (int i = tid; i < n1; i += TPB) lam[i] = (double)ylo[i];
+        __syncthreads();
+        const double floor_c = sqrt((double)n1) * 2.220446049250313e-16;
+        double anrm = -1.0;
+        for (int it = 0; it < 10; ++it) {
+            // r = w - A^T lambda  (column i of A dotted with lambda)
+            double rmax = 0.0, lmax = 0.0, cmax = 0.0;
+            for (int i = tid; i < n1; i += TPB) {
+                const double *col = A + (size_t)i * ld;
+                double s = wv[i], ca = 0.0;
+                for (int j = 0; j < n1; ++j) {
+                    s -= col[j] * lam[j];
+                    ca += fabs(col[j]);
+                }
+                tmp[i] = s;
+                rmax = fmax(rmax, fabs(s));
+                lmax = fmax(lmax, fabs(lam[i]));
+                cmax = fmax(cmax, ca);
+            }
+            rmax = wave_max(rmax);
+            lmax = wave_max(lmax);
+            cmax = wave_max(cmax);
+            if (lane == 0) {
+                red[0][wave] = rmax;
+                red[1][wave] = lmax;
+                part[wave] = cmax;
+            }
+            __syncthreads();
+            rmax = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+            lmax = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+            if (anrm < 0.0) anrm = fmax(fmax(part[0], part[1]), fmax(part[2], part[3]));
+            __syncthreads();
+            if (rmax <= floor_c * anrm * lmax) break;   // ||A^T||_inf = max column sum
+            for (int i = tid; i < n1; i += TPB) ylo[i] = (float)tmp[i];
+            __syncthreads();
+            solve_transposed<float, float>(LU, ld, n1, perm, ylo, tlo, sblk, partf);
+            double dmax = 0.0, ln = 0.0;
+            for (int i = tid; i < n1; i += TPB) {
+                const double d = (double)ylo[i];
+                lam[i] += d;
+                dmax = fmax(dmax, fabs(d));
+                ln = fmax(ln, fabs(lam[i]));
+            }
+            dmax = wave_max(dmax);
+            ln = wave_max(ln);
+            if (lane == 0) {
+                red[0][wave] = dmax;
+                red[1][wave] = ln;
+            }
+            __syncthreads();
+            dmax = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+            ln = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+            __syncthreads();
+            if (dmax <= 1e-12 * ln) break;
+        }
+    }
+
+    // ---- pass 1: control points (dG/dm), one thread per row j -------------
+    for (int j = tid; j < N; j += TPB) {
+        const double mx = 0.5 * (sx[j] + sx[j + 1]), my = 0.5 * (sy[j] + sy[j + 1]);
+        double ax = 0.0, ay = 0.0;
+        double d1x = mx - sx[0], d1y = my - sy[0];
+        double l1 = log(d1x * d1x + d1y * d1y);
+        for (int i = 0; i < N; ++i) {
+            const double d2x = mx - sx[i + 1], d2y = my - sy[i + 1];
+            const double l2 = log(d2x * d2x + d2y * d2y);
+            if (i != j) {
+                const double hx = sx[i + 1] - sx[i], hy = sy[i + 1] - sy[i];
+                const double iL = 1.0 / sqrt(hx * hx + hy * hy);
+                const double tx = hx * iL, ty = hy * iL;
+                const double cr = d1x * d2y - d1y * d2x;
+                const double th = atan2(cr, d1x * d2x + d1y * d2y);
+                const double hl = 0.5 * (l1 - l2);
+                const double xb = xbar[i];
+                // (l1-l2)/2 t - th n, n = (ty, -tx)
+                ax += xb * (hl * tx - th * ty);
+                ay += xb * (hl * ty + th * tx);
+            }
+            d1x = d2x;
+            d1y = d2y;
+            l1 = l2;
+        }
+        const double c = -kInv2Pi * lam[j];
+        gmx[j] = c * ax;
+        gmy[j] = c * ay;
+    }
+    __syncthreads();
+
+    // ---- pass 2: panels (dG/dA, dG/dB), one thread per panel i ------------
+    double *gBx = tmp;   // tmp is free once lambda is known
+    __shared__ double gBy[PANEL_NMAX], gAx[PANEL_NMAX], gAy[PANEL_NMAX];
+    for (int i = tid; i < N; i += TPB) {
+        const double Ax = sx[i], Ay = sy[i], Bx = sx[i + 1], By = sy[i + 1];
+        const double hx = Bx - Ax, hy = By - Ay;
+        const double L = sqrt(hx * hx + hy * hy), iL = 1.0 / L;
+        const double tx = hx * iL, ty = hy * iL, nx = ty, ny = -tx;
+        double bx = 0.0, by = 0.0, sx_ = 0.0, sy_ = 0.0;   // sum lambda dG/dB, sum lambda dG/dm
+        for (int j = 0; j < N; ++j) {
+            const double cj = lam[j];
+            if (j == i) {
+                // diagonal: G_ii depends on the panel length only, so
+                // dG_ii/dB = dG_ii/dL t and dG_ii/dA = -dG_ii/dL t (no m term)
+                const double dGdL = -kInv2Pi * log(0.5 * L);
+                bx += cj * dGdL * tx;
+                by += cj * dGdL * ty;
+                continue;
+            }
+            const double mx = 0.5 * (sx[j] + sx[j + 1]), my = 0.5 * (sy[j] + sy[j + 1]);
+            const double d1x = mx - Ax, d1y = my - Ay, d2x = mx - Bx, d2y = my - By;
+            const double l1 = log(d1x * d1x + d1y * d1y), l2 = log(d2x * d2x + d2y * d2y);
+            const double cr = d1x * d2y - d1y * d2x;
+            const double th = atan2(cr, d1x * d2x + d1y * d2y);
+            const double hl = 0.5 * (l1 - l2);
+            const double xi = d1x * tx + d1y * ty, eta = d1x * nx + d1y * ny;
+            const double G = -kInv4Pi * iL * ((d1x * hx + d1y * hy) * l1 - (d2x * hx + d2y * hy) * l2 -
+                                              2.0 * L * L + 2.0 * cr * th);
+            // dG/dm
+            const double mxg = -kInv2Pi * (hl * tx - th * nx), myg = -kInv2Pi * (hl * ty - th * ny);
+            // dG/dB
+            const double it = xi * hl - L - eta * th, in = -xi * th - eta * hl;
+            const double bgx = kInv2Pi * iL * (it * tx + in * nx) + G * iL * tx;
+            const double bgy = kInv2Pi * iL * (it * ty + in * ny) + G * iL * ty;
+            bx += cj * bgx;
+            by += cj * bgy;
+            sx_ += cj * mxg;
+            sy_ += cj * myg;
+        }
+        const double xb = xbar[i];
+        // dG/dA = -dG/dm - dG/dB off the diagonal; on the diagonal dA = -dB.
+        gBx[i] = xb * bx;   // (tmp holds gBx from here on)
+        gBy[i] = xb * by;
+        gAx[i] = -xb * (sx_ + bx);
+        gAy[i] = -xb * (sy_ + by);
+    }
+    __syncthreads();
+
+    // ---- node gradients --------------------------------------------------------
+    for (int k = tid; k <= N; k += TPB) {
+        double gx = 0.0, gy = 0.0;
+        if (k >= 1) {   // panel k-1 ends at node k; control point k-1
+            const int i = k - 1;
+            const double hx = sx[i + 1] - sx[i], hy = sy[i + 1] - sy[i];
+            const double iL = 1.0 / sqrt(hx * hx + hy * hy);
+            const double e = wscale * xbar[i];
+            gx += e * hx * iL - gBx[i];
+            gy += e * hy * iL - gBy[i];
+            gx += 0.5 * (lam[i] * vinf * S - gmx[i]);
+            gy += 0.5 * (-lam[i] * vinf * Cc - gmy[i]);
+        }
+        if (k < N) {    // panel k starts at node k; control point k
+            const int i = k;
+            const double hx = sx[i + 1] - sx[i], hy = sy[i + 1] - sy[i];
+            const double iL = 1.0 / sqrt(hx * hx + hy * hy);
+            const double e = wscale * xbar[i];
+            gx += -e * hx * iL - gAx[i];
+            gy += -e * hy * iL - gAy[i];
+            gx += 0.5 * (lam[i] * vinf * S - gmx[i]);
+            gy += 0.5 * (-lam[i] * vinf * Cc - gmy[i]);
+        }
+        out[2 * k] = gx;
+        out[2 * k + 1] = gy;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const WsView &v, int32_t B, int32_t, int32_t mixed, const double *xy,
+                          const double *dcl, double *dxy, hipStream_t stream) {
+    if (mixed)
+        adjoint_kernel<float><<<B, TPB, 0, stream>>>(v, xy, dcl, dxy);
+    else
+        adjoint_kernel<double><<<B, TPB, 0, stream>>>(v, xy, dcl, dxy);
+    return hipGetLastError();
 }
 
 }  // namespace panel

@@ -23,6 +23,7 @@
 #include <climits>
 
 #include "panel_internal.hpp"
+#include "wave.hpp"
 
 namespace panel {
 namespace {
@@ -67,32 +68,51 @@ __device__ inline bool better(double va, int ia, double vb, int ib) {
     return va > vb || (va == vb && ia < ib);
 }
 
-// ---- triangular solves on one vector held in LDS ---------------------------
+// ---- triangular solves on one vector held in LDS -----------------------------
+// The matrix stays in global memory; each 64x64 diagonal block is staged in
+// LDS (sblk, column-major, 64 x 64) and solved by one wavefront (lane = row)
+// with reciprocals of the diagonal computed up front and the solved entry
+// broadcast through a scalar register; the other rows are then updated by
+// the whole workgroup.
 
 // Back substitution U x = y (U upper, column-major in global memory), y in LDS.
 template <typename T, typename V>
-__device__ void trsv_upper(const T *U, int ld, int n, V *y) {
+__device__ void trsv_upper(const T *U, int ld, int n, V *y, T *sblk) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = (n + SB - 1) / SB;
     for (int blk = nblk - 1; blk >= 0; --blk) {
-        const int rb = blk * SB, re = min(rb + SB, n);
+        const int rb = blk * SB, w = min(SB, n - rb);
+        for (int idx = tid; idx < SB * SB; idx += TPB) {
+            const int c = idx >> 6, r = idx & 63;
+            sblk[idx] = (c < w && r <= c) ? U[(size_t)(rb + c) * ld + rb + r] : T(0);
+        }
+        __syncthreads();
         if (wave == 0) {
-            const int r = rb + lane;
-            V yi = (r < re) ? y[r] : V(0);
-            for (int j = re - 1; j >= rb; --j) {
-                const V uij = (r < j) ? V(U[(size_t)j * ld + r]) : V(0);
-                V xj = (r == j) ? yi / V(U[(size_t)j * ld + j]) : V(0);
-                xj = __shfl(xj, j - rb);
-                if (r == j) yi = xj;
-                if (r < j) yi -= uij * xj;
+            V yi = (lane < w) ? y[rb + lane] : V(0);
+            const V dinv = (lane < w) ? V(1) / V(sblk[lane * SB + lane]) : V(0);
+            for (int j = w - 1; j >= 0; --j) {
+                if (lane == j) yi *= dinv;
+                const V xj = readlane_t(yi, j);
+                if (lane < j) yi -= V(sblk[j * SB + lane]) * xj;
             }
-            if (r < re) y[r] = yi;
+            if (lane < w) y[rb + lane] = yi;
         }
         __syncthreads();
         for (int r = tid; r < rb; r += TPB) {
-            V s = y[r];
-            for (int j = rb; j < re; ++j) s -= V(U[(size_t)j * ld + r]) * y[j];
-            y[r] = s;
+            const T *up = U + (size_t)rb * ld + r;
+            if (w == SB) {   // every block but the last, partial one
+                V s0 = y[r], s1 = V(0);
+#pragma unroll 16
+                for (int j = 0; j < SB; j += 2) {
+                    s0 -= V(up[(size_t)j * ld]) * y[rb + j];
+                    s1 -= V(up[(size_t)(j + 1) * ld]) * y[rb + j + 1];
+                }
+                y[r] = s0 + s1;
+            } else {
+                V s = y[r];
+                for (int j = 0; j < w; ++j) s -= V(up[(size_t)j * ld]) * y[rb + j];
+                y[r] = s;
+            }
         }
         __syncthreads();
     }
@@ -100,150 +120,174 @@ __device__ void trsv_upper(const T *U, int ld, int n, V *y) {
 
 // Forward substitution L y = b (unit lower), y in LDS.
 template <typename T, typename V>
-__device__ void trsv_lower_unit(const T *L, int ld, int n, V *y) {
+__device__ void trsv_lower_unit(const T *L, int ld, int n, V *y, T *sblk) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = (n + SB - 1) / SB;
     for (int blk = 0; blk < nblk; ++blk) {
-        const int rb = blk * SB, re = min(rb + SB, n);
-        if (wave == 0) {
-            const int r = rb + lane;
-            V yi = (r < re) ? y[r] : V(0);
-            for (int j = rb; j < re; ++j) {
-                const V lij = (r > j && r < re) ? V(L[(size_t)j * ld + r]) : V(0);
-                const V xj = __shfl(yi, j - rb);
-                if (r > j) yi -= lij * xj;
-            }
-            if (r < re) y[r] = yi;
+        const int rb = blk * SB, w = min(SB, n - rb);
+        for (int idx = tid; idx < SB * SB; idx += TPB) {
+            const int c = idx >> 6, r = idx & 63;
+            sblk[idx] = (c < w && r < w && r > c) ? L[(size_t)(rb + c) * ld + rb + r] : T(0);
         }
         __syncthreads();
-        for (int r = re + tid; r < n; r += TPB) {
-            V s = y[r];
-            for (int j = rb; j < re; ++j) s -= V(L[(size_t)j * ld + r]) * y[j];
-            y[r] = s;
+        if (wave == 0) {
+            V yi = (lane < w) ? y[rb + lane] : V(0);
+            for (int j = 0; j < w; ++j) {
+                const V xj = readlane_t(yi, j);
+                if (lane > j) yi -= V(sblk[j * SB + lane]) * xj;
+            }
+            if (lane < w) y[rb + lane] = yi;
+        }
+        __syncthreads();
+        for (int r = rb + w + tid; r < n; r += TPB) {
+            // rows below a block exist only when the block is full (w == SB)
+            V s0 = y[r], s1 = V(0);
+            const T *lp = L + (size_t)rb * ld + r;
+#pragma unroll 16
+            for (int j = 0; j < SB; j += 2) {
+                s0 -= V(lp[(size_t)j * ld]) * y[rb + j];
+                s1 -= V(lp[(size_t)(j + 1) * ld]) * y[rb + j + 1];
+            }
+            y[r] = s0 + s1;
         }
         __syncthreads();
     }
 }
 
-// One column step of the panel factorisation: pivot search over rows
-// g..n-1 of column C, row exchange through LDS, scaling and rank-1 update of
-// the thread's own rows.  C is a template parameter so the register array p
-// is only ever indexed with constants.
+// LDS scratch of one workgroup's panel factorisation.
+template <typename T, int NB> struct PanelLds {
+    T crow[2][TPB / 64][NB];   // each wavefront's pivot candidate row (double-buffered)
+    T grow[2][NB];             // row g (the one the pivot replaces)
+    double cval[2][TPB / 64];  // candidate |a|
+    int cidx[2][TPB / 64];     // candidate row index
+    int piv[NB];               // pivot row chosen at each column of the panel
+};
+
+// One column step of the panel factorisation.  Rows are held one per thread
+// (row k0 + tid + TPB q in p[q][.]); C is a compile-time column index so the
+// register array is only indexed with constants.  One barrier per column:
+// every wavefront publishes its best candidate together with the whole
+// candidate row, and the owner of row g publishes row g, so after the
+// barrier each thread can perform the exchange and the rank-1 update on its
+// own rows.  The LDS slots are double-buffered by column parity.
 template <typename T, int NB, int R, int C>
-__device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int nb, int n, int &info,
-                                           T *s_prow, T *s_srow, double *s_cval, int *s_cidx,
-                                           int *s_piv) {
+__device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int n, int &info,
+                                           PanelLds<T, NB> &L) {
+    constexpr int buf = C & 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = k0 + C;
+    // this thread's candidate: largest |a| among its rows >= g (rows grow
+    // with q, so a strict comparison keeps the lowest index on ties)
     double best = -1.0;
-    int bidx = INT_MAX;
+    int bidx = INT_MAX, bq = 0;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int r = k0 + tid + TPB * q;
-        if (r >= g && r < n) {
-            const double a = fabs((double)p[q][C]);
-            if (a > best) {
-                best = a;
-                bidx = r;
-            }
+        const double a = fabs((double)p[q][C]);
+        if (r >= g && r < n && a > best) {
+            best = a;
+            bidx = r;
+            bq = q;
         }
     }
+    // this wavefront's candidate: exact maximum, lowest row index on ties
+    const double wbest = wave_max(best);
+    const unsigned long long tie = __ballot(best == wbest);
+    int wlane = __ffsll((long long)tie) - 1;
+    int widx = __builtin_amdgcn_readlane(bidx, wlane);
+    if (__popcll(tie) > 1) {   // rare: several lanes hold the maximum
+        int cand = (best == wbest) ? bidx : INT_MAX;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bidx, off);
-        if (better(ob, oi, best, bidx)) {
-            best = ob;
-            bidx = oi;
-        }
+        for (int off = 32; off > 0; off >>= 1) cand = min(cand, __shfl_xor(cand, off));
+        widx = cand;
+        wlane = __ffsll((long long)__ballot(bidx == widx && best == wbest)) - 1;
     }
-    if (lane == 0) {
-        s_cval[wave] = best;
-        s_cidx[wave] = bidx;
-    }
-    __syncthreads();
-    best = s_cval[0];
-    bidx = s_cidx[0];
-#pragma unroll
-    for (int w = 1; w < TPB / 64; ++w) {
-        if (better(s_cval[w], s_cidx[w], best, bidx)) {
-            best = s_cval[w];
-            bidx = s_cidx[w];
-        }
-    }
-    // best == 0: the column is zero at and below the diagonal (exact zero
-    // pivot); no candidate at all (NaN column) is treated alike.
-    const bool zero = !(best > 0.0) || bidx == INT_MAX;
-    const int pr = zero ? g : bidx;
-    const int pown = (pr - k0) & (TPB - 1), pq = (pr - k0) / TPB;
-    if (tid == pown) {
+    if (!(wbest >= 0.0)) widx = INT_MAX;   // no row of this wavefront is eligible
+    if (lane == wlane) {
+        L.cval[buf][wave] = wbest;
+        L.cidx[buf][wave] = widx;
 #pragma unroll
         for (int q = 0; q < R; ++q)
-            if (q == pq) {
+            if (q == bq) {
 #pragma unroll
-                for (int cc = 0; cc < NB; ++cc) s_prow[cc] = p[q][cc];
+                for (int cc = 0; cc < NB; ++cc) L.crow[buf][wave][cc] = p[q][cc];
             }
     }
     if (tid == C) {
 #pragma unroll
-        for (int cc = 0; cc < NB; ++cc) s_srow[cc] = p[0][cc];
-    }
-    if (tid == 0) s_piv[C] = pr;
-    __syncthreads();
-    if (!zero) {
-        if (pr != g) {
-            if (tid == pown) {
-#pragma unroll
-                for (int q = 0; q < R; ++q)
-                    if (q == pq) {
-#pragma unroll
-                        for (int cc = 0; cc < NB; ++cc) p[q][cc] = s_srow[cc];
-                    }
-            }
-            if (tid == C) {
-#pragma unroll
-                for (int cc = 0; cc < NB; ++cc) p[0][cc] = s_prow[cc];
-            }
-        }
-        const T pv = s_prow[C];
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int r = k0 + tid + TPB * q;
-            if (r > g && r < n) {
-                const T l = p[q][C] / pv;
-                p[q][C] = l;
-#pragma unroll
-                for (int cc = C + 1; cc < NB; ++cc) p[q][cc] -= l * s_prow[cc];
-            }
-        }
-    } else if (info == 0) {
-        info = g + 1;
+        for (int cc = 0; cc < NB; ++cc) L.grow[buf][cc] = p[0][cc];
     }
     __syncthreads();
+    double pv = L.cval[buf][0];
+    int pr = L.cidx[buf][0], pw = 0;
+#pragma unroll
+    for (int w = 1; w < TPB / 64; ++w) {
+        const double v = L.cval[buf][w];
+        const int i = L.cidx[buf][w];
+        if (better(v, i, pv, pr)) {
+            pv = v;
+            pr = i;
+            pw = w;
+        }
+    }
+    // pv == 0: the column is zero at and below the diagonal (exact zero
+    // pivot, LAPACK skips the step); no candidate at all (NaN column) alike.
+    const bool zero = !(pv > 0.0) || pr == INT_MAX;
+    if (tid == 0) L.piv[C] = zero ? g : pr;
+    if (zero) {
+        if (info == 0) info = g + 1;
+        return;
+    }
+    const T *u = L.crow[buf][pw];
+    if (pr != g) {
+        const int pown = (pr - k0) & (TPB - 1), pq = (pr - k0) / TPB;
+        if (tid == pown) {
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                if (q == pq) {
+#pragma unroll
+                    for (int cc = 0; cc < NB; ++cc) p[q][cc] = L.grow[buf][cc];
+                }
+        }
+        if (tid == C) {
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc) p[0][cc] = u[cc];
+        }
+    }
+    const T piv = u[C];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = k0 + tid + TPB * q;
+        if (r > g && r < n) {
+            const T l = p[q][C] / piv;
+            p[q][C] = l;
+#pragma unroll
+            for (int cc = C + 1; cc < NB; ++cc) p[q][cc] -= l * u[cc];
+        }
+    }
 }
 
 template <typename T, int NB, int R, int C>
 __device__ __forceinline__ void panel_steps(T (&p)[R][NB], int k0, int nb, int n, int &info,
-                                            T *s_prow, T *s_srow, double *s_cval, int *s_cidx,
-                                            int *s_piv) {
+                                            PanelLds<T, NB> &L) {
     if constexpr (C < NB) {
         if (C < nb) {
-            panel_step<T, NB, R, C>(p, k0, nb, n, info, s_prow, s_srow, s_cval, s_cidx, s_piv);
-            panel_steps<T, NB, R, C + 1>(p, k0, nb, n, info, s_prow, s_srow, s_cval, s_cidx, s_piv);
+            panel_step<T, NB, R, C>(p, k0, n, info, L);
+            panel_steps<T, NB, R, C + 1>(p, k0, nb, n, info, L);
         }
     }
 }
 
 template <typename T, int NB, int R>
-__global__ __launch_bounds__(TPB) void lu_kernel(WsView v, int32_t *__restrict__ info_out) {
+__global__ __launch_bounds__(TPB, 2) void lu_kernel(WsView v, int32_t *__restrict__ info_out) {
     const int b = v.order[blockIdx.x];
     const AirfoilMeta mt = v.meta[b];
     const int n = mt.n1, ld = mt.ld, ncols = mt.n1 + mt.K;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *X = v.x + mt.x_off;
 
     if (v.flag[b] != 0) {   // screened out by the assembly
         if (tid == 0) info_out[b] = -1;
-        double *X = v.x + mt.x_off;
         for (int i = tid; i < n * mt.K; i += TPB) X[i] = __builtin_nan("");
         return;
     }
@@ -251,13 +295,9 @@ __global__ __launch_bounds__(TPB) void lu_kernel(WsView v, int32_t *__restrict__
     T *A = sys_base<T>(v, mt);
     int32_t *piv = v.piv + mt.piv_off;
 
-    __shared__ T s_prow[NB];
-    __shared__ T s_srow[NB];
+    __shared__ PanelLds<T, NB> L;
     __shared__ T s_L11[NB][NB + 1];
     __shared__ T s_U[NB][CH];
-    __shared__ double s_cval[TPB / 64];
-    __shared__ int s_cidx[TPB / 64];
-    __shared__ int s_piv[NB];
     int info = 0;
 
     T p[R][NB];
@@ -265,42 +305,52 @@ __global__ __launch_bounds__(TPB) void lu_kernel(WsView v, int32_t *__restrict__
     for (int k0 = 0; k0 < n; k0 += NB) {
         const int nb = min(NB, n - k0);
 
-        // ---- 1. panel into registers (row k0 + tid + TPB*q) -------------
+        // ---- 1. panel rows k0..n-1 into registers ------------------------
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const int r = k0 + tid + TPB * q;
+            const int rr = r < n ? r : n - 1;
 #pragma unroll
-            for (int cc = 0; cc < NB; ++cc)
-                p[q][cc] = (r < n && cc < nb) ? A[(size_t)(k0 + cc) * ld + r] : T(0);
+            for (int cc = 0; cc < NB; ++cc) {
+                const T t = A[(size_t)min(k0 + cc, n - 1) * ld + rr];
+                p[q][cc] = (r < n && cc < nb) ? t : T(0);
+            }
         }
 
-        // ---- panel factorisation (column index fixed at compile time) ----
-        panel_steps<T, NB, R, 0>(p, k0, nb, n, info, s_prow, s_srow, s_cval, s_cidx, s_piv);
+        // ---- 2. factorise the panel ---------------------------------------
+        panel_steps<T, NB, R, 0>(p, k0, nb, n, info, L);
+        __syncthreads();
 
-        // ---- panel back to memory, L11 and pivots to LDS ----------------
+        // ---- 3. panel back to memory, L11 to LDS, pivots out -------------
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const int r = k0 + tid + TPB * q;
             if (r < n) {
+                if (nb == NB) {
 #pragma unroll
-                for (int cc = 0; cc < NB; ++cc)
-                    if (cc < nb) A[(size_t)(k0 + cc) * ld + r] = p[q][cc];
+                    for (int cc = 0; cc < NB; ++cc) A[(size_t)(k0 + cc) * ld + r] = p[q][cc];
+                } else {
+#pragma unroll
+                    for (int cc = 0; cc < NB; ++cc)
+                        if (cc < nb) A[(size_t)(k0 + cc) * ld + r] = p[q][cc];
+                }
             }
         }
         if (tid < NB) {
 #pragma unroll
             for (int cc = 0; cc < NB; ++cc) s_L11[tid][cc] = (tid < nb) ? p[0][cc] : T(0);
-            if (tid < nb) piv[k0 + tid] = s_piv[tid];
+            if (tid < nb) piv[k0 + tid] = L.piv[tid];
         }
         __syncthreads();
 
-        // ---- 2. row exchanges on every column outside the panel -----------
+        // ---- 4. the panel's row exchanges on every other column ------------
+        // (each thread owns whole columns; exchanges are rare for this system,
+        // so the sequential per-column loop costs little)
         for (int j = tid; j < ncols - nb; j += TPB) {
             const int col = j < k0 ? j : j + nb;
             T *cp = A + (size_t)col * ld;
             for (int c = 0; c < nb; ++c) {
-                const int pr = s_piv[c];
-                const int g = k0 + c;
+                const int pr = L.piv[c], g = k0 + c;
                 if (pr != g) {
                     const T t0 = cp[g];
                     cp[g] = cp[pr];
@@ -310,63 +360,87 @@ __global__ __launch_bounds__(TPB) void lu_kernel(WsView v, int32_t *__restrict__
         }
         __syncthreads();
 
-        // ---- 3./4. U12 and the trailing update, CH columns at a time -----
+        // ---- 5. U12 = L11^{-1} A12 and A22 -= L21 U12, CH columns at a time
         const int rows0 = k0 + nb;
+        const int mrows = n - rows0;
         for (int cs = rows0; cs < ncols; cs += CH) {
             const int cw = min(CH, ncols - cs);
             {
-                // U12 = L11^{-1} A12 for this chunk, one column per thread, kept
-                // in the thread's own LDS column (also the GEMM's B operand).
-                const int col = cs + tid;
+                T u[NB];
+                // rows k0..k0+NB-1 always lie inside the column (ld is a
+                // multiple of NB); rows past n are zero padding
+                T *cp = A + (size_t)(cs + tid) * ld + k0;
                 if (tid < cw) {
-                    T *cp = A + (size_t)col * ld + k0;
-                    for (int r = 0; r < NB; ++r) s_U[r][tid] = (r < nb) ? cp[r] : T(0);
-                    for (int r = 1; r < nb; ++r) {
-                        T s = s_U[r][tid];
-                        for (int q = 0; q < r; ++q) s -= s_L11[r][q] * s_U[q][tid];
-                        s_U[r][tid] = s;
+#pragma unroll
+                    for (int r = 0; r < NB; ++r) {
+                        const T t = cp[r];
+                        u[r] = (r < nb) ? t : T(0);
                     }
-                    for (int r = 0; r < nb; ++r) cp[r] = s_U[r][tid];
+#pragma unroll
+                    for (int c = 0; c < NB - 1; ++c) {
+                        const T uc = u[c];
+#pragma unroll
+                        for (int r = c + 1; r < NB; ++r) u[r] -= s_L11[r][c] * uc;
+                    }
+#pragma unroll
+                    for (int r = 0; r < NB; ++r) cp[r] = u[r];
                 } else {
-                    for (int r = 0; r < NB; ++r) s_U[r][tid] = T(0);
+#pragma unroll
+                    for (int r = 0; r < NB; ++r) u[r] = T(0);
                 }
+#pragma unroll
+                for (int r = 0; r < NB; ++r) s_U[r][tid] = u[r];
             }
             __syncthreads();
 
-            const int mrows = n - rows0;
             if (mrows > 0) {
                 const int nrt = (mrows + 15) >> 4;
                 const int nct = (cw + 15) >> 4;
                 const int i16 = lane & 15, k4 = lane >> 4;
-                for (int t = wave; t < nrt * nct; t += TPB / 64) {
-                    const int ct = t / nrt, rt = t - ct * nrt;
+                for (int rt = wave; rt < nrt; rt += TPB / 64) {
                     const int r0 = rows0 + 16 * rt;
-                    const int cl = 16 * ct + i16;          // column within the chunk
-                    const bool cok = cl < cw;
-                    T *ccol = A + (size_t)(cs + cl) * ld + r0;
-                    typename Acc<T>::type acc;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) acc[e] = cok ? ccol[Acc<T>::row(lane, e)] : T(0);
+                    // this row tile's L21 fragments stay in registers for all column tiles
+                    T af[NB / 4];
                     const T *lcol = A + (size_t)k0 * ld + r0 + i16;
+                    // (a trailing block exists only when the panel is full: nb == NB)
 #pragma unroll
-                    for (int kk = 0; kk < NB; kk += 4) {
-                        const int kx = kk + k4;
-                        const T a = (kx < nb) ? -lcol[(size_t)kx * ld] : T(0);
-                        const T bb = s_U[kx][cl < CH ? cl : 0];
-                        acc = mfma16(a, bb, acc);
-                    }
-                    if (cok) {
+                    for (int kk = 0; kk < NB / 4; ++kk) af[kk] = -lcol[(size_t)(4 * kk + k4) * ld];
+                    // four column tiles in flight per wavefront
+                    for (int ct0 = 0; ct0 < nct; ct0 += 4) {
+                        typename Acc<T>::type acc[4];
+                        T *ccol[4];
+                        bool cok[4];
+                        int cl[4];
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) ccol[Acc<T>::row(lane, e)] = acc[e];
+                        for (int t = 0; t < 4; ++t) {
+                            cl[t] = 16 * (ct0 + t) + i16;
+                            cok[t] = cl[t] < cw;
+                            ccol[t] = A + (size_t)(cs + (cok[t] ? cl[t] : cw - 1)) * ld + r0;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) acc[t][e] = ccol[t][Acc<T>::row(lane, e)];
+                        }
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int cls = cok[t] ? cl[t] : 0;
+#pragma unroll
+                            for (int kk = 0; kk < NB / 4; ++kk)
+                                acc[t] = mfma16(af[kk], s_U[4 * kk + k4][cls], acc[t]);
+                        }
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            if (cok[t]) {
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) ccol[t][Acc<T>::row(lane, e)] = acc[t][e];
+                            }
                     }
                 }
             }
             __syncthreads();
         }
     }
-    // ---- back substitution for the K right-hand sides ------------------
+
+    // ---- back substitution for the K right-hand sides ----------------------
     // The right-hand-side columns now hold L^{-1} P b; solve U x = that.
-    double *X = v.x + mt.x_off;
     if (tid == 0) {
         info_out[b] = info;
         v.flag[b] = info;
@@ -375,12 +449,13 @@ __global__ __launch_bounds__(TPB) void lu_kernel(WsView v, int32_t *__restrict__
         for (int i = tid; i < n * mt.K; i += TPB) X[i] = __builtin_nan("");
         return;
     }
-    T *y = &s_U[0][0];   // n <= PANEL_NMAX + 1 <= NB * CH values
+    __shared__ T y[PANEL_NMAX + 1];
+    T *sblk = &s_U[0][0];   // SB x SB values (NB * CH >= SB * SB)
     for (int k = 0; k < mt.K; ++k) {
         __syncthreads();
         for (int i = tid; i < n; i += TPB) y[i] = A[(size_t)(n + k) * ld + i];
         __syncthreads();
-        trsv_upper<T, T>(A, ld, n, y);
+        trsv_upper<T, T>(A, ld, n, y, sblk);
         for (int i = tid; i < n; i += TPB) X[(size_t)k * n + i] = (double)y[i];
     }
 }
@@ -412,6 +487,7 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
     __shared__ float sd[PANEL_NMAX + 1];
     __shared__ int perm[PANEL_NMAX + 1];
     __shared__ double red[3][TPB / 64];
+    __shared__ float sblk[SB * SB];
     if (tid == 0) {
         for (int i = 0; i < n; ++i) perm[i] = i;
         for (int i = 0; i < n; ++i) {
@@ -480,8 +556,8 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
             }
             for (int i = tid; i < n; i += TPB) sd[i] = (float)sr[perm[i]];
             __syncthreads();
-            trsv_lower_unit<float, float>(LU, ld, n, sd);
-            trsv_upper<float, float>(LU, ld, n, sd);
+            trsv_lower_unit<float, float>(LU, ld, n, sd, sblk);
+            trsv_upper<float, float>(LU, ld, n, sd, sblk);
             double dmax = 0.0, xn = 0.0, unused = 0.0;
             for (int i = tid; i < n; i += TPB) {
                 const double d = (double)sd[i];
@@ -515,9 +591,9 @@ template <typename T>
 hipError_t launch_lu_any(const WsView &v, int32_t B, int32_t max_n1, int32_t *info, hipStream_t s) {
     const int R = (max_n1 + TPB - 1) / TPB;
     if (R <= 1)
-        launch_lu<T, 32, 1>(v, B, info, s);
+        launch_lu<T, 16, 1>(v, B, info, s);
     else if (R == 2)
-        launch_lu<T, 32, 2>(v, B, info, s);
+        launch_lu<T, 16, 2>(v, B, info, s);
     else if (R == 3)
         launch_lu<T, 16, 3>(v, B, info, s);
     else

@@ -107,7 +107,7 @@ panel_status panel_plan_create(int32_t B, const int32_t *h_node_offsets,
             m.N = h_node_offsets[b + 1] - h_node_offsets[b] - 1;
             m.K = h_alpha_offsets[b + 1] - h_alpha_offsets[b];
             m.n1 = m.N + 1;
-            m.ld = (m.n1 + 15) & ~15;
+            m.ld = (m.n1 + 31) & ~31;
             m.node_off = h_node_offsets[b];
             m.alpha_off = h_alpha_offsets[b];
             m.panel_off = h_node_offsets[b] - b;

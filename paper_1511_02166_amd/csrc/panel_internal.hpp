@@ -19,7 +19,7 @@ struct AirfoilMeta {
     int32_t N;          // panels
     int32_t K;          // angles of attack
     int32_t n1;         // system order N + 1
-    int32_t ld;         // leading dimension (n1 rounded up to 16)
+    int32_t ld;         // leading dimension (n1 rounded up to 32)
     int32_t node_off;   // first node of the airfoil in xy
     int32_t alpha_off;  // first angle in alpha / cl
     int32_t panel_off;  // first panel in the geometry cache (node_off - b)
