@@ -31,6 +31,8 @@ namespace {
 constexpr int TPB = 256;   // threads per workgroup (4 wavefronts)
 constexpr int CH = 256;    // trailing columns per U12 chunk
 constexpr int SB = 64;     // rows per diagonal block in the triangular solves
+constexpr int SP = 64;     // super-panel width (rank of the big trailing update)
+constexpr int CT = 64;     // columns per LDS chunk of the rank-SP update
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
@@ -278,12 +280,101 @@ __device__ __forceinline__ void panel_steps(T (&p)[R][NB], int k0, int nb, int n
     }
 }
 
+// U12 = L11^{-1} A12 for columns [cs, cs + cw) (cw <= CH), rows k0..k0+nb:
+// one thread per column, the column kept in registers, L11 (unit lower) read
+// from LDS; the result goes back to memory and, k-major, to Us (ld CH + 4)
+// as the B operand of the following update.
+template <typename T, int NB>
+__device__ __forceinline__ void trsm_cols(T *A, int ld, int k0, int nb, int cs, int cw,
+                                          const T (*sL)[NB + 1], T *Us) {
+    const int tid = threadIdx.x;
+    T u[NB];
+    // rows k0..k0+NB-1 always lie inside the column (ld is a multiple of NB);
+    // rows past n are zero padding
+    T *cp = A + (size_t)(cs + tid) * ld + k0;
+    if (tid < cw) {
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            const T t = cp[r];
+            u[r] = (r < nb) ? t : T(0);
+        }
+#pragma unroll
+        for (int c = 0; c < NB - 1; ++c) {
+            const T uc = u[c];
+#pragma unroll
+            for (int r = c + 1; r < NB; ++r) u[r] -= sL[r][c] * uc;
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) cp[r] = u[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < NB; ++r) u[r] = T(0);
+    }
+    if (tid < CH) {
+#pragma unroll
+        for (int r = 0; r < NB; ++r) Us[r * (CH + 4) + tid] = u[r];
+    }
+}
+
+// C[rows rowA..rowEnd, cols colA..colA+ncol) -= A[rows, kb..kb+KD) * B, on the
+// matrix cores.  rowA is a multiple of 16 and rowEnd <= ld (tiles may run
+// into the zero padding rows).  B lives in LDS: B(k, c) = Bs[k * ldb + c]
+// when BK is true (k-major) and Bs[c * ldb + k] otherwise, c counted from
+// bcol0.  Each wavefront takes row tiles; it keeps the tile's A fragments in
+// registers and streams four 16x16 C tiles at a time.
+template <typename T, int KD, bool BK>
+__device__ __forceinline__ void gemm_sub(T *A, int ld, int rowA, int rowEnd, int colA, int ncol, int kb,
+                                         const T *Bs, int ldb, int bcol0) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i16 = lane & 15, k4 = lane >> 4;
+    const int nrt = (rowEnd - rowA + 15) >> 4;
+    const int nct = (ncol + 15) >> 4;
+    if (nrt <= 0 || ncol <= 0) return;
+    for (int rt = wave; rt < nrt; rt += TPB / 64) {
+        const int r0 = rowA + 16 * rt;
+        T af[KD / 4];
+        const T *lcol = A + (size_t)kb * ld + r0 + i16;
+#pragma unroll
+        for (int kk = 0; kk < KD / 4; ++kk) af[kk] = -lcol[(size_t)(4 * kk + k4) * ld];
+        for (int ct0 = 0; ct0 < nct; ct0 += 4) {
+            typename Acc<T>::type acc[4];
+            T *ccol[4];
+            bool cok[4];
+            int cl[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                cl[t] = 16 * (ct0 + t) + i16;
+                cok[t] = cl[t] < ncol;
+                ccol[t] = A + (size_t)(colA + (cok[t] ? cl[t] : ncol - 1)) * ld + r0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[t][e] = ccol[t][Acc<T>::row(lane, e)];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int bc = bcol0 + (cok[t] ? cl[t] : 0);
+#pragma unroll
+                for (int kk = 0; kk < KD / 4; ++kk) {
+                    const int k = 4 * kk + k4;
+                    const T bv = BK ? Bs[k * ldb + bc] : Bs[bc * ldb + k];
+                    acc[t] = mfma16(af[kk], bv, acc[t]);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (cok[t]) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ccol[t][Acc<T>::row(lane, e)] = acc[t][e];
+                }
+        }
+    }
+}
+
 template <typename T, int NB, int R>
 __global__ __launch_bounds__(TPB, 2) void lu_kernel(WsView v, int32_t *__restrict__ info_out) {
     const int b = v.order[blockIdx.x];
     const AirfoilMeta mt = v.meta[b];
     const int n = mt.n1, ld = mt.ld, ncols = mt.n1 + mt.K;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     double *X = v.x + mt.x_off;
 
     if (v.flag[b] != 0) {   // screened out by the assembly
@@ -297,12 +388,17 @@ __global__ __launch_bounds__(TPB, 2) void lu_kernel(WsView v, int32_t *__restric
 
     __shared__ PanelLds<T, NB> L;
     __shared__ T s_L11[NB][NB + 1];
-    __shared__ T s_U[NB][CH];
+    __shared__ T s_U[NB][CH + 4];   // also holds the CT x (SP + 1) band of step 6
     int info = 0;
 
     T p[R][NB];
 
-    for (int k0 = 0; k0 < n; k0 += NB) {
+    // Super-panels of SP columns; inside, NB-column pivot panels update the
+    // super-panel's own columns fully but only the super-panel's rows of the
+    // columns to its right; those columns get one rank-SP update at the end.
+    for (int K0 = 0; K0 < n; K0 += SP) {
+    const int kend = min(K0 + SP, n);
+    for (int k0 = K0; k0 < kend; k0 += NB) {
         const int nb = min(NB, n - k0);
 
         // ---- 1. panel rows k0..n-1 into registers ------------------------
@@ -360,83 +456,52 @@ __global__ __launch_bounds__(TPB, 2) void lu_kernel(WsView v, int32_t *__restric
         }
         __syncthreads();
 
-        // ---- 5. U12 = L11^{-1} A12 and A22 -= L21 U12, CH columns at a time
+        // ---- 5. the panel's update of the super-panel columns to its right
         const int rows0 = k0 + nb;
-        const int mrows = n - rows0;
-        for (int cs = rows0; cs < ncols; cs += CH) {
-            const int cw = min(CH, ncols - cs);
-            {
-                T u[NB];
-                // rows k0..k0+NB-1 always lie inside the column (ld is a
-                // multiple of NB); rows past n are zero padding
-                T *cp = A + (size_t)(cs + tid) * ld + k0;
-                if (tid < cw) {
-#pragma unroll
-                    for (int r = 0; r < NB; ++r) {
-                        const T t = cp[r];
-                        u[r] = (r < nb) ? t : T(0);
-                    }
-#pragma unroll
-                    for (int c = 0; c < NB - 1; ++c) {
-                        const T uc = u[c];
-#pragma unroll
-                        for (int r = c + 1; r < NB; ++r) u[r] -= s_L11[r][c] * uc;
-                    }
-#pragma unroll
-                    for (int r = 0; r < NB; ++r) cp[r] = u[r];
-                } else {
-#pragma unroll
-                    for (int r = 0; r < NB; ++r) u[r] = T(0);
-                }
-#pragma unroll
-                for (int r = 0; r < NB; ++r) s_U[r][tid] = u[r];
-            }
+        if (rows0 < kend) {
+            trsm_cols<T, NB>(A, ld, k0, nb, rows0, kend - rows0, s_L11, &s_U[0][0]);
             __syncthreads();
-
-            if (mrows > 0) {
-                const int nrt = (mrows + 15) >> 4;
-                const int nct = (cw + 15) >> 4;
-                const int i16 = lane & 15, k4 = lane >> 4;
-                for (int rt = wave; rt < nrt; rt += TPB / 64) {
-                    const int r0 = rows0 + 16 * rt;
-                    // this row tile's L21 fragments stay in registers for all column tiles
-                    T af[NB / 4];
-                    const T *lcol = A + (size_t)k0 * ld + r0 + i16;
-                    // (a trailing block exists only when the panel is full: nb == NB)
-#pragma unroll
-                    for (int kk = 0; kk < NB / 4; ++kk) af[kk] = -lcol[(size_t)(4 * kk + k4) * ld];
-                    // four column tiles in flight per wavefront
-                    for (int ct0 = 0; ct0 < nct; ct0 += 4) {
-                        typename Acc<T>::type acc[4];
-                        T *ccol[4];
-                        bool cok[4];
-                        int cl[4];
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) {
-                            cl[t] = 16 * (ct0 + t) + i16;
-                            cok[t] = cl[t] < cw;
-                            ccol[t] = A + (size_t)(cs + (cok[t] ? cl[t] : cw - 1)) * ld + r0;
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) acc[t][e] = ccol[t][Acc<T>::row(lane, e)];
-                        }
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) {
-                            const int cls = cok[t] ? cl[t] : 0;
-#pragma unroll
-                            for (int kk = 0; kk < NB / 4; ++kk)
-                                acc[t] = mfma16(af[kk], s_U[4 * kk + k4][cls], acc[t]);
-                        }
-#pragma unroll
-                        for (int t = 0; t < 4; ++t)
-                            if (cok[t]) {
-#pragma unroll
-                                for (int e = 0; e < 4; ++e) ccol[t][Acc<T>::row(lane, e)] = acc[t][e];
-                            }
-                    }
-                }
-            }
+            if (rows0 < n) gemm_sub<T, NB, true>(A, ld, rows0, n, rows0, kend - rows0, k0, &s_U[0][0], CH + 4, 0);
             __syncthreads();
         }
+    }
+    // ---- 6. columns right of the super-panel.  They saw only row exchanges so
+    // far (all their rows are equally stale, so the exchanges keep them
+    // consistent); now apply the super-panel's four 16-column steps to its
+    // own rows (triangular solve + rank-16 update of the rows below within
+    // the band), then one rank-SP update of everything below the band.
+    if (kend < ncols) {
+        for (int k0 = K0; k0 < kend; k0 += NB) {
+            const int nb = min(NB, kend - k0);
+            if (tid < NB) {
+                const T *lrow = A + (size_t)k0 * ld + k0 + tid;
+#pragma unroll
+                for (int cc = 0; cc < NB; ++cc) s_L11[tid][cc] = (tid < nb && cc < nb) ? lrow[(size_t)cc * ld] : T(0);
+            }
+            __syncthreads();
+            for (int cs = kend; cs < ncols; cs += CH) {
+                const int cw = min(CH, ncols - cs);
+                trsm_cols<T, NB>(A, ld, k0, nb, cs, cw, s_L11, &s_U[0][0]);
+                __syncthreads();
+                if (k0 + nb < kend)
+                    gemm_sub<T, NB, true>(A, ld, k0 + nb, kend, cs, cw, k0, &s_U[0][0], CH + 4, 0);
+                __syncthreads();
+            }
+        }
+        if (kend < n) {
+            T *Bs = &s_U[0][0];   // CT x SP band of U, column-major (ld SP+1)
+            for (int cs = kend; cs < ncols; cs += CT) {
+                const int cw = min(CT, ncols - cs);
+                for (int idx = tid; idx < SP * CT; idx += TPB) {
+                    const int c = idx / SP, r = idx - c * SP;
+                    Bs[c * (SP + 1) + r] = (c < cw) ? A[(size_t)(cs + c) * ld + K0 + r] : T(0);
+                }
+                __syncthreads();
+                gemm_sub<T, SP, false>(A, ld, kend, n, cs, cw, K0, Bs, SP + 1, 0);
+                __syncthreads();
+            }
+        }
+    }
     }
 
     // ---- back substitution for the K right-hand sides ----------------------

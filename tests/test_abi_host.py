@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every symbol include/panel.h declares, and
+reject bad arguments synchronously, before any HIP call is made.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "panel.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1511_02166_amd as P
+    if not os.path.exists(P.lib_path()):
+        from paper_1511_02166_amd import build
+        build.build()
+    return P.load_library()
+
+
+def _declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"\b(panel_[a-z0-9_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for n in ("panel_plan_create", "panel_workspace_size", "panel_assemble", "panel_factor_solve",
+              "panel_forces", "panel_adjoint", "panel_naca4", "panel_status_str"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for n in _declared_functions():
+        assert hasattr(lib, n), n
+
+
+def _plan(lib, noff, aoff, prec=0):
+    noff = np.ascontiguousarray(noff, dtype=np.int32)
+    aoff = np.ascontiguousarray(aoff, dtype=np.int32)
+    h = C.c_void_p()
+    st = lib.panel_plan_create(len(noff) - 1, noff.ctypes.data_as(C.c_void_p),
+                               aoff.ctypes.data_as(C.c_void_p), prec, C.byref(h))
+    return st, h
+
+
+def test_plan_validation(lib):
+    import paper_1511_02166_amd as P
+    st, h = _plan(lib, [0, 129, 258], [0, 1, 3])
+    assert st == P._binding.PANEL_OK and h.value
+    size = C.c_size_t()
+    assert lib.panel_workspace_size(h, C.byref(size)) == 0
+    # ld = 160 for n1 = 129; two systems of 160 x (129 + K) doubles at least
+    assert size.value > 8 * 160 * (130 + 132)
+    lib.panel_plan_destroy(h)
+    bad = [([0, 3], [0, 1]),              # too few panels
+           ([0, 2000], [0, 1]),           # too many panels
+           ([1, 130], [0, 1]),            # offsets not starting at 0
+           ([0, 129], [0, 0]),            # no angle
+           ([0, 129], [0, 40])]           # too many angles
+    for noff, aoff in bad:
+        st, h = _plan(lib, noff, aoff)
+        assert st == P._binding.PANEL_EINVAL, (noff, aoff)
+        assert lib.panel_last_error()
+    st, h = _plan(lib, [0, 129], [0, 1], prec=7)
+    assert st == P._binding.PANEL_EINVAL
+
+
+def test_entry_points_reject_bad_arguments_before_hip(lib):
+    import paper_1511_02166_amd as P
+    EINVAL = P._binding.PANEL_EINVAL
+    st, h = _plan(lib, [0, 129], [0, 1], prec=1)
+    assert st == 0
+    fake = C.c_void_p(0x100000)          # never dereferenced: checks fail first
+    odd = C.c_void_p(0x100003)
+    assert lib.panel_assemble(h, None, fake, None, C.c_double(1.0), fake, None) == EINVAL
+    assert lib.panel_assemble(h, odd, fake, None, C.c_double(1.0), fake, None) == EINVAL
+    assert lib.panel_assemble(h, fake, fake, None, C.c_double(-1.0), fake, None) == EINVAL
+    assert lib.panel_assemble(h, fake, fake, None, C.c_double(float("nan")), fake, None) == EINVAL
+    assert lib.panel_assemble(h, fake, fake, None, C.c_double(1.0), C.c_void_p(0x100008), None) == EINVAL
+    assert lib.panel_factor_solve(h, fake, C.c_double(0.0), 10, fake, None) == EINVAL
+    assert lib.panel_factor_solve(h, fake, C.c_double(1e-10), 101, fake, None) == EINVAL
+    assert lib.panel_factor_solve(h, fake, C.c_double(1e-10), 3, None, None) == EINVAL
+    assert lib.panel_forces(h, fake, None, None, None, None, None) == EINVAL
+    assert lib.panel_adjoint(h, fake, fake, None, fake, None) == EINVAL
+    assert lib.panel_naca4(0, fake, 1, fake, fake, None) == EINVAL
+    assert lib.panel_naca4_vjp(2, fake, 1, fake, None, fake, None) == EINVAL
+    lib.panel_plan_destroy(h)
+
+
+def test_layout_and_status_strings(lib):
+    import paper_1511_02166_amd as P
+    st, h = _plan(lib, [0, 257, 514], [0, 1, 5])
+    d = (C.c_int64 * 8)()
+    assert lib.panel_workspace_layout(h, 1, d) == 0
+    assert d[4] == 257 and d[5] == 288 and d[6] == 4
+    assert d[0] % 128 == 0
+    assert lib.panel_workspace_layout(h, 2, d) == P._binding.PANEL_EINVAL
+    lib.panel_plan_destroy(h)
+    for s in range(5):
+        assert P.panel_status_str(s).startswith("PANEL_")
