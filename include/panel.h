@@ -174,6 +174,15 @@ panel_status panel_naca4(int32_t B, const int32_t *node_off, int32_t closed_te,
 panel_status panel_naca4_vjp(int32_t B, const int32_t *node_off, int32_t closed_te,
                              const double *mpt, const double *dxy, double *dmpt, void *stream);
 
+/* Diagnostic: evaluates the FP64 logarithm and two-argument arctangent the
+ * assembly and adjoint kernels use (the library's own, not the device libm),
+ * for accuracy tests:
+ *   log_out[i] = log(x[i])          (x[i] > 0; NULL log_out skips it)
+ *   atan2_out[i] = atan2(y[i], x[i])  (NULL atan2_out skips it)
+ * All arrays are device arrays of n doubles.                               */
+panel_status panel_math_eval(int32_t n, const double *x, const double *y, double *log_out,
+                             double *atan2_out, void *stream);
+
 /* Static description of a status code. */
 const char *panel_status_str(int32_t status);
 

@@ -24,6 +24,7 @@ from ._binding import (  # noqa: F401
     panel_factor_solve,
     panel_forces,
     panel_last_error,
+    panel_math_eval,
     panel_naca4,
     panel_naca4_vjp,
     panel_plan_create,
@@ -40,5 +41,5 @@ __all__ = [
     "PanelError", "Plan", "PanelSolver", "panel_cl", "naca_cl",
     "panel_plan_create", "panel_plan_destroy", "panel_workspace_size", "panel_workspace_init", "panel_workspace_layout",
     "panel_assemble", "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
-    "panel_naca4_vjp", "panel_status_str", "panel_last_error", "load_library", "lib_path",
+    "panel_naca4_vjp", "panel_math_eval", "panel_status_str", "panel_last_error", "load_library", "lib_path",
 ]

@@ -48,6 +48,7 @@ def load_library():
     L.panel_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
     L.panel_naca4.argtypes = [i32, vp, i32, vp, vp, vp]
     L.panel_naca4_vjp.argtypes = [i32, vp, i32, vp, vp, vp, vp]
+    L.panel_math_eval.argtypes = [i32, vp, vp, vp, vp, vp]
     L.panel_status_str.argtypes = [i32]
     L.panel_status_str.restype = C.c_char_p
     L.panel_last_error.argtypes = []
@@ -55,7 +56,7 @@ def load_library():
     for name in ("panel_plan_create", "panel_workspace_size", "panel_workspace_init",
                  "panel_workspace_layout", "panel_assemble",
                  "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
-                 "panel_naca4_vjp"):
+                 "panel_naca4_vjp", "panel_math_eval"):
         getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -214,3 +215,11 @@ def panel_naca4_vjp(B, node_off, closed_te, mpt, dxy, dmpt, stream=None):
     _check(load_library().panel_naca4_vjp(int(B), _ptr(node_off, torch.int32, "node_off"),
                                           int(bool(closed_te)), _ptr(mpt, d, "mpt"), _ptr(dxy, d, "dxy"),
                                           _ptr(dmpt, d, "dmpt"), _stream(stream)))
+
+
+def panel_math_eval(x, y, log_out, atan2_out, stream=None):
+    import torch
+    d = torch.float64
+    _check(load_library().panel_math_eval(int(x.numel()), _ptr(x, d, "x"), _ptr(y, d, "y", True),
+                                          _ptr(log_out, d, "log_out", True),
+                                          _ptr(atan2_out, d, "atan2_out", True), _stream(stream)))

@@ -24,6 +24,7 @@
 // thread per panel) the endpoint derivatives; no cross-thread reductions.
 #include <climits>
 
+#include "fastmath.hpp"
 #include "panel_internal.hpp"
 #include "wave.hpp"
 
@@ -273,16 +274,16 @@ __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__
         const double mx = 0.5 * (sx[j] + sx[j + 1]), my = 0.5 * (sy[j] + sy[j + 1]);
         double ax = 0.0, ay = 0.0;
         double d1x = mx - sx[0], d1y = my - sy[0];
-        double l1 = log(d1x * d1x + d1y * d1y);
+        double l1 = plog(d1x * d1x + d1y * d1y);
         for (int i = 0; i < N; ++i) {
             const double d2x = mx - sx[i + 1], d2y = my - sy[i + 1];
-            const double l2 = log(d2x * d2x + d2y * d2y);
+            const double l2 = plog(d2x * d2x + d2y * d2y);
             if (i != j) {
                 const double hx = sx[i + 1] - sx[i], hy = sy[i + 1] - sy[i];
                 const double iL = 1.0 / sqrt(hx * hx + hy * hy);
                 const double tx = hx * iL, ty = hy * iL;
                 const double cr = d1x * d2y - d1y * d2x;
-                const double th = atan2(cr, d1x * d2x + d1y * d2y);
+                const double th = patan2(cr, d1x * d2x + d1y * d2y);
                 const double hl = 0.5 * (l1 - l2);
                 const double xb = xbar[i];
                 // (l1-l2)/2 t - th n, n = (ty, -tx)
@@ -313,16 +314,16 @@ __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__
             if (j == i) {
                 // diagonal: G_ii depends on the panel length only, so
                 // dG_ii/dB = dG_ii/dL t and dG_ii/dA = -dG_ii/dL t (no m term)
-                const double dGdL = -kInv2Pi * log(0.5 * L);
+                const double dGdL = -kInv2Pi * plog(0.5 * L);
                 bx += cj * dGdL * tx;
                 by += cj * dGdL * ty;
                 continue;
             }
             const double mx = 0.5 * (sx[j] + sx[j + 1]), my = 0.5 * (sy[j] + sy[j + 1]);
             const double d1x = mx - Ax, d1y = my - Ay, d2x = mx - Bx, d2y = my - By;
-            const double l1 = log(d1x * d1x + d1y * d1y), l2 = log(d2x * d2x + d2y * d2y);
+            const double l1 = plog(d1x * d1x + d1y * d1y), l2 = plog(d2x * d2x + d2y * d2y);
             const double cr = d1x * d2y - d1y * d2x;
-            const double th = atan2(cr, d1x * d2x + d1y * d2y);
+            const double th = patan2(cr, d1x * d2x + d1y * d2y);
             const double hl = 0.5 * (l1 - l2);
             const double xi = d1x * tx + d1y * ty, eta = d1x * nx + d1y * ny;
             const double G = -kInv4Pi * iL * ((d1x * hx + d1y * hy) * l1 - (d2x * hx + d2y * hy) * l2 -

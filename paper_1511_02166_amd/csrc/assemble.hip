@@ -13,12 +13,15 @@
 // which is the closed form of the integral with the difference of the two
 // arctangents folded into one (the angle subtended by the panel) and the
 // logarithm of |m_j - P_{i+1}|^2 shared between panels i and i+1.  The
-// self-influence is the midpoint limit (L/2pi)(1 - log(L/2)).
+// self-influence is the midpoint limit (L/2pi)(1 - log(L/2)), evaluated with
+// the shared logarithm (|m_j - P_j| = L/2).  log and atan2 are the library's
+// own (fastmath.hpp).
 //
 // One workgroup covers COLS consecutive columns of one airfoil's augmented
 // matrix [M | rhs] (column-major, leading dimension ld, rows n1..ld-1
 // zero-filled); a thread owns one row at a time, so consecutive lanes write
 // consecutive addresses of a column.
+#include "fastmath.hpp"
 #include "panel_internal.hpp"
 
 namespace panel {
@@ -87,6 +90,60 @@ __global__ __launch_bounds__(256) void assemble_kernel(WsView v, const double *_
     float *A32 = MIXED ? v.a32 + mt.a_off : nullptr;
     const int cend = min(c0 + COLS, ncols);
 
+    if (c0 + COLS <= N) {
+        // Interior block: all COLS columns are panel columns.  Branch-free;
+        // the diagonal entry reuses the shared logarithm, since
+        // log(L/2) = log|m_j - P_j|^2 / 2 on the diagonal.
+        __shared__ double shx[COLS], shy[COLS], sL2[COLS], siL[COLS];
+        if (threadIdx.x < COLS) {
+            const int c = c0 + threadIdx.x;
+            const double hx = sx[c + 1] - sx[c], hy = sy[c + 1] - sy[c];
+            const double L2 = hx * hx + hy * hy;
+            shx[threadIdx.x] = hx;
+            shy[threadIdx.x] = hy;
+            sL2[threadIdx.x] = L2;
+            siL[threadIdx.x] = 1.0 / sqrt(L2);
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < ld; j += blockDim.x) {
+            double *Aj = A + (size_t)c0 * ld + j;
+            float *A32j = MIXED ? A32 + (size_t)c0 * ld + j : nullptr;
+            if (j < N) {
+                const double mx = 0.5 * (sx[j] + sx[j + 1]);
+                const double my = 0.5 * (sy[j] + sy[j + 1]);
+                double d1x = mx - sx[c0], d1y = my - sy[c0];
+                double l1 = plog(d1x * d1x + d1y * d1y);
+#pragma unroll 2
+                for (int cc = 0; cc < COLS; ++cc) {
+                    const int c = c0 + cc;
+                    const double d2x = mx - sx[c + 1], d2y = my - sy[c + 1];
+                    const double l2 = plog(d2x * d2x + d2y * d2y);
+                    const double hx = shx[cc], hy = shy[cc], L2 = sL2[cc], iL = siL[cc];
+                    const double dot1 = d1x * hx + d1y * hy;
+                    const double cr = d1x * d2y - d1y * d2x;
+                    const double dd = d1x * d2x + d1y * d2y;
+                    const double ang = patan2(cr, dd);
+                    const double gen = -kInv4Pi * iL * (dot1 * l1 - (dot1 - L2) * l2 - 2.0 * L2 + 2.0 * cr * ang);
+                    const double diag = kInv2Pi * L2 * iL * (1.0 - 0.5 * l1);
+                    const double g = (c == j) ? diag : gen;
+                    Aj[(size_t)cc * ld] = g;
+                    if (MIXED) A32j[(size_t)cc * ld] = (float)g;
+                    d1x = d2x;
+                    d1y = d2y;
+                    l1 = l2;
+                }
+            } else {
+                for (int cc = 0; cc < COLS; ++cc) {
+                    const int c = c0 + cc;
+                    const double g = (j == N && (c == 0 || c == N - 1)) ? 1.0 : 0.0;
+                    Aj[(size_t)cc * ld] = g;
+                    if (MIXED) A32j[(size_t)cc * ld] = (float)g;
+                }
+            }
+        }
+        return;
+    }
+
     for (int j = threadIdx.x; j < ld; j += blockDim.x) {
         double val[COLS];
         if (j < N) {
@@ -97,7 +154,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(WsView v, const double *_
             if (c0 < N) {
                 d1x = mx - sx[c0];
                 d1y = my - sy[c0];
-                l1 = log(d1x * d1x + d1y * d1y);
+                l1 = plog(d1x * d1x + d1y * d1y);
             }
 #pragma unroll
             for (int cc = 0; cc < COLS; ++cc) {
@@ -105,19 +162,18 @@ __global__ __launch_bounds__(256) void assemble_kernel(WsView v, const double *_
                 double g = 0.0;
                 if (c < N) {
                     const double d2x = mx - sx[c + 1], d2y = my - sy[c + 1];
-                    const double l2 = log(d2x * d2x + d2y * d2y);
+                    const double l2 = plog(d2x * d2x + d2y * d2y);
                     const double hx = sx[c + 1] - sx[c], hy = sy[c + 1] - sy[c];
                     const double L2 = hx * hx + hy * hy;
                     const double L = sqrt(L2);
                     if (c == j) {
-                        g = L * kInv2Pi * (1.0 - log(0.5 * L));
+                        g = L * kInv2Pi * (1.0 - 0.5 * l1);
                     } else {
                         const double dot1 = d1x * hx + d1y * hy;
-                        const double dot2 = d2x * hx + d2y * hy;
                         const double cr = d1x * d2y - d1y * d2x;
                         const double dd = d1x * d2x + d1y * d2y;
-                        const double ang = atan2(cr, dd);
-                        g = -kInv4Pi / L * (dot1 * l1 - dot2 * l2 - 2.0 * L2 + 2.0 * cr * ang);
+                        const double ang = patan2(cr, dd);
+                        g = -kInv4Pi / L * (dot1 * l1 - (dot1 - L2) * l2 - 2.0 * L2 + 2.0 * cr * ang);
                     }
                     d1x = d2x;
                     d1y = d2y;

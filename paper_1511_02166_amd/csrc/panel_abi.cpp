@@ -286,4 +286,15 @@ panel_status panel_naca4_vjp(int32_t B, const int32_t *node_off, int32_t closed_
     return check_hip(e, "naca4 vjp launch");
 }
 
+panel_status panel_math_eval(int32_t n, const double *x, const double *y, double *log_out,
+                             double *atan2_out, void *stream) {
+    if (n < 0) return fail(PANEL_EINVAL, "n must be >= 0");
+    if (n == 0) return ok();
+    if (!x || (atan2_out && !y) || (!log_out && !atan2_out)) return fail(PANEL_EINVAL, "NULL argument");
+    if (!aligned8(x) || (y && !aligned8(y)) || (log_out && !aligned8(log_out)) || (atan2_out && !aligned8(atan2_out)))
+        return fail(PANEL_EINVAL, "arrays must be 8-byte aligned");
+    hipError_t e = launch_math_eval(n, x, y, log_out, atan2_out, static_cast<hipStream_t>(stream));
+    return check_hip(e, "math eval launch");
+}
+
 }  // extern "C"

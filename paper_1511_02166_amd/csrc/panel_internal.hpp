@@ -92,6 +92,8 @@ hipError_t launch_factor_solve(const WsView &v, int32_t B, int32_t max_n1, int32
                                double tol, int32_t max_iter, int32_t *info, hipStream_t stream);
 hipError_t launch_forces(const WsView &v, int32_t B, int32_t max_k, double *gamma, double *cp,
                          double *cl, double *cl_p, hipStream_t stream);
+hipError_t launch_math_eval(int32_t n, const double *x, const double *y, double *lg, double *at,
+                            hipStream_t stream);
 hipError_t launch_adjoint(const WsView &v, int32_t B, int32_t max_n1, int32_t mixed,
                           const double *xy, const double *dcl, double *dxy, hipStream_t stream);
 

@@ -163,7 +163,11 @@ def test_uneven_batch_matches_oracle(precision):
 
 
 def test_closed_form_geometries_identical_inputs():
-    # Cylinder and Joukowski nodes from the shared input generator, fed to both sides.
+    # Cylinder and Joukowski nodes from the shared input generator, fed to both
+    # sides.  Cusped Joukowski sections are much worse conditioned than the
+    # NACA workloads (kappa 3e7 vs 1.6e6 at N = 256), so entry differences of
+    # a few ulp move Cp by up to ~kappa * 1e-17: the tolerance is
+    # max(base, 2e-17 kappa) per geometry, kappa measured on the oracle matrix.
     import paper_1511_02166_amd as P
     _say("cylinder / joukowski parity")
     nodes = [synth.circle_nodes(64), synth.joukowski_nodes(128), synth.circle_nodes(200, 0.3, 1.0, -2.0),
@@ -171,13 +175,24 @@ def test_closed_form_geometries_identical_inputs():
     xy_flat, noff = synth.pack_nodes(nodes)
     al = [np.array([0.0, 5 * DEG]), np.array([4 * DEG]), np.array([-3 * DEG, 1 * DEG, 7 * DEG]),
           np.array([2 * DEG])]
-    w = synth.Workload("closed-form", np.zeros(4), np.zeros(4), np.zeros(4),
-                       (np.diff(noff) - 1).astype(np.int32), al)
-    for prec, tol in ((P.PANEL_FP64, TOL64), (P.PANEL_FP32_REFINE, TOL32R)):
-        s, got = _run(w, prec, xy_flat)
+    kappa = [np.linalg.cond(oracle.assemble(nd, [0.0])[0]) for nd in nodes]
+    for prec, base in ((P.PANEL_FP64, TOL64), (P.PANEL_FP32_REFINE, TOL32R)):
+        s, got = _run(w := synth.Workload("closed-form", np.zeros(4), np.zeros(4), np.zeros(4),
+                                          (np.diff(noff) - 1).astype(np.int32), al), prec, xy_flat)
         ref = _oracle(w, xy_flat)
-        e = _errors(got, ref, w)
-        assert e["cl"] < tol and e["cp"] < tol, (prec, e)
+        for b in range(4):
+            wb = w.subset([b])
+            sl_a = slice(w.alpha_offsets()[b], w.alpha_offsets()[b + 1])
+            so = np.concatenate([[0], np.cumsum((np.diff(noff) - 1) * np.diff(w.alpha_offsets()))])
+            sl_s = slice(so[b], so[b + 1])
+            gb = {k: got[k][sl_a] for k in ("cl", "cl_p")}
+            gb.update({k: got[k][sl_s] for k in ("cp", "gamma")})
+            rb = {k: ref[k][sl_a] for k in ("cl", "cl_p")}
+            rb.update({k: ref[k][sl_s] for k in ("cp", "gamma")})
+            e = _errors(gb, rb, wb)
+            tol = max(base, 2e-17 * kappa[b])
+            _say(f"  prec {prec} geom {b} kappa {kappa[b]:.1e} tol {tol:.1e} errors {e}")
+            assert e["cl"] < tol and e["cp"] < tol, (prec, b, e)
 
 
 def test_pivots_match_oracle_on_kutta_system():
