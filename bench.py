@@ -29,6 +29,18 @@ sys.path.insert(0, HERE)
 METRIC = "airfoil solves/s at N=256 (FP64 vs FP32+refine) + Cl err vs FP64 oracle"
 PEAK = {"f64": 78.6e12, "f32": 157.3e12, "hbm": 8.0e12}
 
+# FP64 operations per off-diagonal influence entry of the assembly kernel,
+# counted from its compiled gfx950 code: one logarithm (27 FP64 instructions,
+# 17 of them FMA), one arctangent (34, 15 FMA) and the closed-form
+# combination; 39 FMA x 2 + 40 other FP64 instructions in total.
+ASM_FLOPS_PER_ENTRY = 118.0
+
+# HBM bytes moved by one launch of the FP64 LU kernel on the 2048 x N=256
+# batch, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's
+# readings (x2.0 and x1.0).  Valid only for the kernel source it was taken
+# on, which is identified by the SHA-256 prefix of csrc/lu.hip.
+LU_TRAFFIC = {"96db77a830f2ad44": 9_070_497_848}
+
 
 def _args():
     ap = argparse.ArgumentParser()
@@ -38,7 +50,8 @@ def _args():
     ap.add_argument("--config", type=int, default=2, help="seeded workload (2 = GA-population batch)")
     ap.add_argument("--batch", type=int, default=None, help="truncate the batch (debugging only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=None, help="airfoils in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="airfoils in the oracle sample (default: the whole batch)")
     ap.add_argument("--no-adjoint", action="store_true")
     return ap.parse_args()
 
@@ -152,21 +165,24 @@ def main():
     lu_ms = r64["factor_solve_ms"]
     asm_ms = r64["assemble_ms"]
     lu_ach = (lu_f + solve_f) / (lu_ms * 1e-3)
-    # assembly: algorithmic FP64 operations per influence entry
-    ASM_OPS_PER_PAIR = 120.0
-    asm_ach = pairs * ASM_OPS_PER_PAIR / (asm_ms * 1e-3)
+    asm_ach = pairs * ASM_FLOPS_PER_ENTRY / (asm_ms * 1e-3)
     kern = {
         "lu_solve_f64": {"bound": "mfma", "achieved": lu_ach / 1e12, "peak": PEAK["f64"] / 1e12,
                          "unit": "TFLOP/s", "frac": lu_ach / PEAK["f64"], "ms": lu_ms,
                          "work": "(2/3)n^3 + 2n^2K flops per airfoil"},
         "assemble_f64": {"bound": "alu", "achieved": asm_ach / 1e12, "peak": PEAK["f64"] / 1e12,
                          "unit": "TFLOP/s", "frac": asm_ach / PEAK["f64"], "ms": asm_ms,
-                         "work": f"{ASM_OPS_PER_PAIR:.0f} FP64 ops per influence entry"},
+                         "work": f"{ASM_FLOPS_PER_ENTRY:.0f} FP64 flops per influence entry"},
     }
     dom = "lu_solve_f64" if lu_ms >= asm_ms else "assemble_f64"
     roof = dict(kern[dom])
+    traffic = None
+    if dom == "lu_solve_f64" and a.config == 2 and a.batch is None:
+        import hashlib
+        with open(os.path.join(os.path.dirname(P.__file__), "csrc", "lu.hip"), "rb") as f:
+            traffic = LU_TRAFFIC.get(hashlib.sha256(f.read()).hexdigest()[:16])
     roof = {"kernel": dom, "bound": roof["bound"], "achieved": roof["achieved"], "peak": roof["peak"],
-            "unit": roof["unit"], "frac": roof["frac"], "traffic": None}
+            "unit": roof["unit"], "frac": roof["frac"], "traffic": traffic}
 
     out = {
         "metric": METRIC,
@@ -196,10 +212,13 @@ def main():
     if not a.no_cpu_baseline:
         import oracle
         nthr = min(os.cpu_count() or 1, 16)
-        S = a.cpu_sample or min(B, 32 * nthr)
+        S = min(B, a.cpu_sample or B)
         idx = np.linspace(0, B - 1, S).astype(int)
         ws = w.subset(idx)
         xy_o, noff_o = oracle.workload_nodes(ws)
+        w0 = ws.subset(np.arange(min(S, nthr)))          # untimed warm-up (pages, threads)
+        x0, n0 = oracle.workload_nodes(w0)
+        oracle.solve_batch(x0, n0, w0.alpha_flat(), w0.alpha_offsets(), nthreads=nthr)
         t0 = time.perf_counter()
         ref = oracle.solve_batch(xy_o, noff_o, ws.alpha_flat(), ws.alpha_offsets(), nthreads=nthr)
         dt = time.perf_counter() - t0
@@ -219,8 +238,9 @@ def main():
         out["fp32_refine"].update(cl_err=e32, cp_err=p32)
         out["cpu_baseline"] = {"value": int(ref["cl"].size) / dt, "unit": "solves/s",
                                "cores": int(ref["threads"]), "kind": "oracle",
-                               "sample": f"{S} airfoils evenly spaced over the batch, full pipeline "
-                                         f"(plain C FP64, OpenMP over airfoils), {dt:.2f} s wall"}
+                               "sample": f"{S} of the {B} airfoils, full pipeline (nodes given; assembly, "
+                                         f"LU, solve, forces in plain C FP64, OpenMP over airfoils), "
+                                         f"{dt:.2f} s wall"}
         out["cl_err_vs_oracle"] = {"fp64": e64, "fp32_refine": e32}
     print(json.dumps(out), flush=True)
 
