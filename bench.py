@@ -53,6 +53,8 @@ def _args():
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="airfoils in the oracle sample (default: the whole batch)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--wave-limit", type=int, default=None,
+                    help="largest system order for the one-wavefront LU (0 = workgroup LU only)")
     return ap.parse_args()
 
 
@@ -85,8 +87,8 @@ def main():
     alpha = torch.as_tensor(w.alpha_flat(), device=dev)
     mpt = torch.as_tensor(w.mpt(), device=dev)
 
-    s64 = P.PanelSolver(noff, aoff, P.PANEL_FP64)
-    s32 = P.PanelSolver(noff, aoff, P.PANEL_FP32_REFINE)
+    s64 = P.PanelSolver(noff, aoff, P.PANEL_FP64, wave_limit=a.wave_limit)
+    s32 = P.PanelSolver(noff, aoff, P.PANEL_FP32_REFINE, wave_limit=a.wave_limit)
     xy = s64.naca4(mpt, True)
     torch.cuda.synchronize()
 

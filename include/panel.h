@@ -88,6 +88,16 @@ panel_status panel_plan_create(int32_t B, const int32_t *h_node_offsets,
 /* Release a plan (NULL is ignored). */
 void panel_plan_destroy(panel_plan *plan);
 
+/* Choose the LU kernel by system order (Sec. 3: many independent dense
+ * factorisations).  Systems with n1 = N_b + 1 <= max_n1 are factored by one
+ * wavefront each; larger ones by a workgroup of four wavefronts each.
+ *   max_n1   0 .. 320; 0 sends every system to the workgroup kernel.
+ *            Default 320.
+ * Both kernels produce LAPACK getrf factors and pivots (largest |a|, lowest
+ * row on ties).  Takes effect at the next panel_workspace_init (the airfoil
+ * order lives in the workspace).  PANEL_EINVAL outside the range.         */
+panel_status panel_plan_set_wave_limit(panel_plan *plan, int32_t max_n1);
+
 /* Bytes of device workspace the plan needs (256-byte aligned base). */
 panel_status panel_workspace_size(const panel_plan *plan, size_t *bytes);
 

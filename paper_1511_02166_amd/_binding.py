@@ -39,6 +39,7 @@ def load_library():
     L.panel_plan_create.argtypes = [i32, vp, vp, i32, C.POINTER(vp)]
     L.panel_plan_destroy.argtypes = [vp]
     L.panel_plan_destroy.restype = None
+    L.panel_plan_set_wave_limit.argtypes = [vp, i32]
     L.panel_workspace_size.argtypes = [vp, C.POINTER(sz)]
     L.panel_workspace_init.argtypes = [vp, vp, vp]
     L.panel_workspace_layout.argtypes = [vp, i32, vp]
@@ -53,7 +54,7 @@ def load_library():
     L.panel_status_str.restype = C.c_char_p
     L.panel_last_error.argtypes = []
     L.panel_last_error.restype = C.c_char_p
-    for name in ("panel_plan_create", "panel_workspace_size", "panel_workspace_init",
+    for name in ("panel_plan_create", "panel_plan_set_wave_limit", "panel_workspace_size", "panel_workspace_init",
                  "panel_workspace_layout", "panel_assemble",
                  "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
                  "panel_naca4_vjp", "panel_math_eval"):
@@ -157,6 +158,11 @@ def panel_plan_destroy(plan: Plan):
     if plan._h is not None and plan._h.value:
         load_library().panel_plan_destroy(plan._h)
     plan._h = None
+
+
+def panel_plan_set_wave_limit(plan: Plan, max_n1: int):
+    """Largest system order factored by one wavefront (0..320; 0 = none)."""
+    _check(load_library().panel_plan_set_wave_limit(plan.handle, int(max_n1)))
 
 
 def panel_workspace_size(plan: Plan) -> int:

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpanel.so")
 ARCH = os.environ.get("PANEL_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["panel_abi.cpp", "geometry.hip", "assemble.hip", "lu.hip", "forces.hip", "adjoint.hip",
+SOURCES = ["panel_abi.cpp", "geometry.hip", "assemble.hip", "lu.hip", "lu_wave.hip", "forces.hip", "adjoint.hip",
            "mathcheck.hip"]
 
 FLAGS = [

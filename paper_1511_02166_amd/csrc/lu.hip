@@ -668,16 +668,18 @@ hipError_t launch_lu_any(const WsView &v, int32_t B, int32_t max_n1, int32_t *in
 
 }  // namespace
 
-hipError_t launch_factor_solve(const WsView &v, int32_t B, int32_t max_n1, int32_t mixed, double tol,
-                               int32_t max_iter, int32_t *info, hipStream_t stream) {
-    hipError_t e;
-    if (!mixed) {
-        e = launch_lu_any<double>(v, B, max_n1, info, stream);
-    } else {
-        e = launch_lu_any<float>(v, B, max_n1, info, stream);
+hipError_t launch_factor_solve(const WsView &v, int32_t B, int32_t n_block, int32_t max_n1_block,
+                               int32_t mixed, double tol, int32_t max_iter, int32_t *info,
+                               hipStream_t stream) {
+    hipError_t e = hipSuccess;
+    if (n_block > 0) {
+        e = mixed ? launch_lu_any<float>(v, n_block, max_n1_block, info, stream)
+                  : launch_lu_any<double>(v, n_block, max_n1_block, info, stream);
         if (e != hipSuccess) return e;
-        refine_kernel<<<B, TPB, 0, stream>>>(v, info, tol, max_iter);
     }
+    e = launch_lu_wave(v, n_block, B - n_block, mixed, info, stream);
+    if (e != hipSuccess) return e;
+    if (mixed) refine_kernel<<<B, TPB, 0, stream>>>(v, info, tol, max_iter);
     return hipGetLastError();
 }
 

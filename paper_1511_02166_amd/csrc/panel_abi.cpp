@@ -19,7 +19,11 @@ struct panel_plan {
     int32_t max_n1 = 0;
     int32_t max_k = 0;
     int32_t max_cols = 0;  // max over airfoils of n1 + K
+    int32_t wave_max_n1 = PANEL_WAVE_MAX_N1;  // largest order given to the one-wavefront LU
+    int32_t n_block = 0;       // airfoils factored by the workgroup LU (first in order)
+    int32_t max_n1_block = 0;  // their largest order
     std::vector<int32_t> node_off, alpha_off;
+    std::vector<double> cost;  // LPT key: (2/3) n1^3 + 2 n1^2 K
     std::vector<char> blob;  // header | meta | order, copied by workspace_init
     WsLayout layout{};
 };
@@ -41,6 +45,31 @@ panel_status ok() {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+// Airfoils for the workgroup LU first, then those for the one-wavefront LU;
+// each group by decreasing cost (longest processing time first), so the
+// in-order dispatch of workgroups is an LPT list schedule within each launch.
+void build_order(panel_plan *p) {
+    const int32_t B = p->B;
+    std::vector<int32_t> order(B);
+    std::vector<char> big(B);
+    p->n_block = 0;
+    p->max_n1_block = 0;
+    for (int32_t b = 0; b < B; ++b) {
+        order[b] = b;
+        const int32_t n1 = p->node_off[b + 1] - p->node_off[b];
+        big[b] = n1 > p->wave_max_n1;
+        if (big[b]) {
+            ++p->n_block;
+            p->max_n1_block = std::max(p->max_n1_block, n1);
+        }
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+        if (big[a] != big[c]) return big[a] > big[c];
+        return p->cost[a] > p->cost[c];
+    });
+    std::memcpy(p->blob.data() + p->layout.order, order.data(), sizeof(int32_t) * B);
+}
 
 panel_status check_hip(hipError_t e, const char *what) {
     if (e != hipSuccess)
@@ -101,7 +130,8 @@ panel_status panel_plan_create(int32_t B, const int32_t *h_node_offsets,
         p->alpha_off.assign(h_alpha_offsets, h_alpha_offsets + B + 1);
         std::vector<AirfoilMeta> meta(B);
         int64_t a_off = 0, x_off = 0, s_off = 0, piv_off = 0;
-        std::vector<double> cost(B);
+        std::vector<double> &cost = p->cost;
+        cost.assign(B, 0.0);
         for (int32_t b = 0; b < B; ++b) {
             AirfoilMeta &m = meta[b];
             m.N = h_node_offsets[b + 1] - h_node_offsets[b] - 1;
@@ -126,12 +156,6 @@ panel_status panel_plan_create(int32_t B, const int32_t *h_node_offsets,
             double n = m.n1;
             cost[b] = n * n * n / 1.5 + 2.0 * n * n * m.K;
         }
-        // Longest-processing-time order: the most expensive airfoils first.
-        std::vector<int32_t> order(B);
-        for (int32_t b = 0; b < B; ++b) order[b] = b;
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int32_t a, int32_t c) { return cost[a] > cost[c]; });
-
         WsLayout &l = p->layout;
         size_t off = align256(sizeof(WsHeader));
         l.meta = off;
@@ -170,7 +194,7 @@ panel_status panel_plan_create(int32_t B, const int32_t *h_node_offsets,
         p->blob.assign(l.flag, 0);
         std::memcpy(p->blob.data(), &hdr, sizeof hdr);
         std::memcpy(p->blob.data() + l.meta, meta.data(), sizeof(AirfoilMeta) * B);
-        std::memcpy(p->blob.data() + l.order, order.data(), sizeof(int32_t) * B);
+        build_order(p);
     } catch (const std::bad_alloc &) {
         delete p;
         return fail(PANEL_ENOMEM, "plan metadata allocation");
@@ -180,6 +204,18 @@ panel_status panel_plan_create(int32_t B, const int32_t *h_node_offsets,
 }
 
 void panel_plan_destroy(panel_plan *plan) { delete plan; }
+
+panel_status panel_plan_set_wave_limit(panel_plan *plan, int32_t max_n1) {
+    if (!plan) return fail(PANEL_EINVAL, "NULL plan");
+    if (max_n1 < 0 || max_n1 > PANEL_WAVE_MAX_N1) {
+        char buf[120];
+        std::snprintf(buf, sizeof buf, "wave limit must be in 0..%d", PANEL_WAVE_MAX_N1);
+        return fail(PANEL_EINVAL, buf);
+    }
+    plan->wave_max_n1 = max_n1;
+    build_order(plan);
+    return ok();
+}
 
 panel_status panel_workspace_layout(const panel_plan *plan, int32_t b, int64_t *h_desc) {
     if (!plan || !h_desc) return fail(PANEL_EINVAL, "NULL argument");
@@ -240,8 +276,8 @@ panel_status panel_factor_solve(const panel_plan *plan, void *ws, double refine_
         if (max_iter < 0 || max_iter > 100) return fail(PANEL_EINVAL, "max_iter must be in 0..100");
     }
     WsView v = ws_view(ws, plan->layout);
-    hipError_t e = launch_factor_solve(v, plan->B, plan->max_n1, mixed, refine_tol, max_iter, info,
-                                       static_cast<hipStream_t>(stream));
+    hipError_t e = launch_factor_solve(v, plan->B, plan->n_block, plan->max_n1_block, mixed, refine_tol,
+                                       max_iter, info, static_cast<hipStream_t>(stream));
     return check_hip(e, "factor/solve launch");
 }
 

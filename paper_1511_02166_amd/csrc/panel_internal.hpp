@@ -88,8 +88,17 @@ hipError_t launch_naca4_vjp(int32_t B, const int32_t *node_off, int32_t closed_t
 hipError_t launch_assemble(const WsView &v, int32_t B, int32_t max_cols, int32_t mixed,
                            const double *xy, const double *alpha, const double *chord, double vinf,
                            hipStream_t stream);
-hipError_t launch_factor_solve(const WsView &v, int32_t B, int32_t max_n1, int32_t mixed,
-                               double tol, int32_t max_iter, int32_t *info, hipStream_t stream);
+// Systems of order up to PANEL_WAVE_MAX_N1 can be factored by one wavefront
+// each (lu_wave.hip); larger ones by a workgroup each (lu.hip).  The plan
+// puts the workgroup-kernel airfoils first in `order` (n_block of them, each
+// group in LPT order).
+constexpr int PANEL_WAVE_RMAX = 5;
+constexpr int PANEL_WAVE_MAX_N1 = 64 * PANEL_WAVE_RMAX;
+hipError_t launch_factor_solve(const WsView &v, int32_t B, int32_t n_block, int32_t max_n1_block,
+                               int32_t mixed, double tol, int32_t max_iter, int32_t *info,
+                               hipStream_t stream);
+hipError_t launch_lu_wave(const WsView &v, int32_t first, int32_t count, int32_t mixed, int32_t *info,
+                          hipStream_t stream);
 hipError_t launch_forces(const WsView &v, int32_t B, int32_t max_k, double *gamma, double *cp,
                          double *cl, double *cl_p, hipStream_t stream);
 hipError_t launch_math_eval(int32_t n, const double *x, const double *y, double *lg, double *at,

@@ -26,9 +26,12 @@ class PanelSolver:
         out = s.solve(xy, alpha)          # dict of gamma, cp, cl, cl_p, info
     """
 
-    def __init__(self, node_offsets, alpha_offsets, precision=B.PANEL_FP64, device="cuda"):
+    def __init__(self, node_offsets, alpha_offsets, precision=B.PANEL_FP64, device="cuda",
+                 wave_limit=None):
         self.device = torch.device(device)
         self.plan = B.Plan(node_offsets, alpha_offsets, precision)
+        if wave_limit is not None:
+            B.panel_plan_set_wave_limit(self.plan, wave_limit)
         self.precision = int(precision)
         p = self.plan
         self._ws_raw, self.ws = _aligned_workspace(p.workspace_size(), self.device)

@@ -71,6 +71,13 @@ def test_plan_validation(lib):
         assert lib.panel_last_error()
     st, h = _plan(lib, [0, 129], [0, 1], prec=7)
     assert st == P._binding.PANEL_EINVAL
+    st, h = _plan(lib, [0, 129], [0, 1])
+    assert lib.panel_plan_set_wave_limit(h, 0) == 0
+    assert lib.panel_plan_set_wave_limit(h, 320) == 0
+    assert lib.panel_plan_set_wave_limit(h, 321) == P._binding.PANEL_EINVAL
+    assert lib.panel_plan_set_wave_limit(h, -1) == P._binding.PANEL_EINVAL
+    assert lib.panel_plan_set_wave_limit(None, 0) == P._binding.PANEL_EINVAL
+    lib.panel_plan_destroy(h)
 
 
 def test_entry_points_reject_bad_arguments_before_hip(lib):

@@ -69,11 +69,11 @@ def _errors(gpu, ref, w):
     return dict(cl=e_cl.max(), cl_p=e_clp.max(), cp=e_cp.max(), gamma=e_g.max())
 
 
-def _run(w, precision, xy_flat=None, refine_tol=1e-10, max_iter=10):
+def _run(w, precision, xy_flat=None, refine_tol=1e-10, max_iter=10, wave_limit=None):
     import paper_1511_02166_amd as P
     torch = _torch()
     xy, alpha = _gpu_inputs(w, xy_flat)
-    s = P.PanelSolver(w.node_offsets(), w.alpha_offsets(), precision)
+    s = P.PanelSolver(w.node_offsets(), w.alpha_offsets(), precision, wave_limit=wave_limit)
     out = s.solve(xy, alpha, refine_tol=refine_tol, max_iter=max_iter)
     torch.cuda.synchronize()
     return s, {k: v.cpu().numpy() for k, v in out.items()}
@@ -122,12 +122,12 @@ def test_assembly_entries_match_oracle():
             assert np.max(np.abs(rhs - Rr)) < 1e-15
 
 
-@pytest.mark.parametrize("cfg,B", [(1, 32), (2, 96)])
-def test_fp64_pipeline_matches_oracle(cfg, B):
+@pytest.mark.parametrize("cfg,B,wave_limit", [(1, 32, None), (2, 96, None), (2, 40, 0)])
+def test_fp64_pipeline_matches_oracle(cfg, B, wave_limit):
     import paper_1511_02166_amd as P
-    _say(f"fp64 pipeline parity: cfg{cfg}[:{B}]")
+    _say(f"fp64 pipeline parity: cfg{cfg}[:{B}], wave_limit={wave_limit}")
     w = synth.workload(cfg, B=B)
-    s, got = _run(w, P.PANEL_FP64)
+    s, got = _run(w, P.PANEL_FP64, wave_limit=wave_limit)
     ref = _oracle(w)
     assert np.all(got["info"] == 0) and np.all(ref["info"] == 0)
     e = _errors(got, ref, w)
@@ -135,12 +135,12 @@ def test_fp64_pipeline_matches_oracle(cfg, B):
     assert e["cl"] < TOL64 and e["cp"] < TOL64 and e["cl_p"] < TOL64, e
 
 
-@pytest.mark.parametrize("cfg,B", [(1, 32), (2, 96)])
-def test_fp32_refined_pipeline_matches_oracle(cfg, B):
+@pytest.mark.parametrize("cfg,B,wave_limit", [(1, 32, None), (2, 96, None), (2, 40, 0)])
+def test_fp32_refined_pipeline_matches_oracle(cfg, B, wave_limit):
     import paper_1511_02166_amd as P
-    _say(f"fp32+refine pipeline parity: cfg{cfg}[:{B}]")
+    _say(f"fp32+refine pipeline parity: cfg{cfg}[:{B}], wave_limit={wave_limit}")
     w = synth.workload(cfg, B=B)
-    s, got = _run(w, P.PANEL_FP32_REFINE)
+    s, got = _run(w, P.PANEL_FP32_REFINE, wave_limit=wave_limit)
     ref = _oracle(w)
     assert np.all(got["info"] == 0)
     e = _errors(got, ref, w)
@@ -266,19 +266,28 @@ def test_graph_replay_matches_eager():
             assert torch.equal(s.cl, eager)
 
 
+# Panel counts for the factor checks: full and partial 64-column super-panels
+# and 16-column tails; 1..5 rows per thread (workgroup kernel, N > 319) and
+# 1..5 rows per lane (wavefront kernel, N <= 319).
+_SIZES_MIXED = [4, 30, 62, 64, 130, 190, 256, 300, 510, 700, 1024]
+_SIZES_WAVE = [4, 15, 16, 17, 31, 62, 63, 64, 65, 100, 127, 128, 129, 191, 192, 193, 255, 256, 257, 300,
+               318, 319]
+
+
 @pytest.mark.parametrize("precision", [0, 1])
-def test_lu_factors_reproduce_matrix(precision):
+@pytest.mark.parametrize("sizes,wave_limit", [(_SIZES_MIXED, None), (_SIZES_WAVE, None),
+                                              (_SIZES_WAVE[::3], 0)],
+                         ids=["mixed-kernels", "wavefront-kernel", "workgroup-kernel"])
+def test_lu_factors_reproduce_matrix(precision, sizes, wave_limit):
     # Direct algebraic check of the stored factors: P A = L U (FP64 to 1e-13,
     # FP32 to its own rounding level), and the right-hand-side columns hold
-    # L^{-1} P b.  Sizes exercise full and partial 64-column super-panels and
-    # the 16-column tail, for 1, 2, 3 and 5 rows per thread.
+    # L^{-1} P b.
     import paper_1511_02166_amd as P
     torch = _torch()
-    sizes = [4, 30, 62, 64, 130, 190, 256, 300, 510, 700, 1024]
-    _say(f"LU factor residual, precision={precision}, N={sizes}")
+    _say(f"LU factor residual, precision={precision}, wave_limit={wave_limit}, N={sizes}")
     xy_flat, noff = synth.joukowski_batch(31, len(sizes), sizes)
     aoff = np.arange(len(sizes) + 1, dtype=np.int32) * 2
-    s = P.PanelSolver(noff, aoff, precision)
+    s = P.PanelSolver(noff, aoff, precision, wave_limit=wave_limit)
     xy = torch.as_tensor(xy_flat, device="cuda")
     al = torch.as_tensor(np.tile([0.03, 0.1], len(sizes)), device="cuda")
     s.assemble(xy, al)
