@@ -54,13 +54,20 @@ typedef float f4w_t __attribute__((ext_vector_type(4)));
 // 4(l>>4) + v for FP32.  Either way one accumulator register of the 64 lanes
 // covers 16 consecutive rows of four columns.
 template <typename T> struct TileMap;
+// For the untransposed products D = M Y of the band solve, D must come out in
+// the layout the B operand uses (lane l, index s holds row 4s + l/16), so
+// the result can feed the next product without leaving the registers.  For
+// FP64 that is D's own layout; for FP32 the rows of M are supplied permuted,
+// row arow(i) in place of row i, which turns D's layout into it.
 template <> struct TileMap<double> {
     typedef d4w_t acc;
     static __device__ inline int col(int lane, int v) { return (lane >> 4) + 4 * v; }
+    static __device__ inline int arow(int i) { return i; }
 };
 template <> struct TileMap<float> {
     typedef f4w_t acc;
     static __device__ inline int col(int lane, int v) { return 4 * (lane >> 4) + v; }
+    static __device__ inline int arow(int i) { return 4 * (i & 3) + (i >> 2); }
 };
 __device__ inline d4w_t mfma_t(double a, double b, d4w_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -84,60 +91,140 @@ __device__ inline int lanes_below(unsigned long long m) {
 
 template <typename T> struct WaveLds {
     T l11[WNB][WNB + 1];     // unit-lower diagonal block of a pivot panel
+    T linv[WSP / WNB][WNB][WNB + 1];   // inverses of the super-panel's diagonal blocks
     int mv_src[2 * WNB];     // row moves of the last panel: row mv_src[m]
     int mv_dst[2 * WNB];     //   ends at position mv_dst[m]
     int nmv;
     int ipiv[WNB];           // LAPACK pivots of the last panel (positions)
 };
 
-// ---- C[r0:r1, c0:c1) -= A[r0:r1, kb:kb+KD) * A[kb:kb+KD, c0:c1) ------------
-// U fragments of WCT columns stay in registers while 16-row tiles of L and C
-// stream through.  Rows past r1 and columns past c1 are clamped for the loads
-// (their results are discarded), never stored.
-template <typename T, int KD>
-__device__ void wave_gemm(T *A, int ld, int r0, int r1, int c0, int c1, int kb) {
-    constexpr int S = KD / 4;
+// ---- block update after pivot panels: band solve + trailing product --------
+// For the columns [c0, c1) and the band of rows [kb, kb + 16 nblk) below
+// which the panels kb.. have been factored (row moves already applied):
+//   U  = L_band^{-1} A[band, c0:c1)      (L_band: unit lower, 16 nblk square)
+//   A[kend:n, c0:c1) -= A[kend:n, band] U      (only if kend < n; then the
+//                                               band is the full 16 NBLK)
+// WCT columns at a time.  The band of those columns is loaded once into
+// B-operand fragments (lane l, index s: row kb + 4s + l/16, column l%16 of a
+// 16-column tile), solved in registers block by block on the matrix cores
+// (X_i = linv_i Y_i, then Y_j -= L_ji X_i), stored once, and kept as the U
+// fragments of the trailing product.  The trailing product streams 16-row
+// tiles of L and C; the next tile's loads are interleaved with the current
+// tile's products (its C block into a second accumulator set, each L
+// fragment into the register the current product has just consumed).  Rows
+// past n / columns past c1 are clamped for the loads and never stored; rows
+// of the band past n are zero padding (linv is the identity there).
+template <typename T, int NBLK>
+__device__ __forceinline__ void wave_update(T *A, int ld, int n, int kb, int kend, int c0, int c1,
+                                            const WaveLds<T> &S, int slot0) {
+    constexpr int S4 = 4 * NBLK;   // k-steps (4 rows each) of the band
     constexpr int NT = WCT / 16;
+    typedef typename TileMap<T>::acc acc_t;
     const int lane = threadIdx.x, i16 = lane & 15, k4 = lane >> 4;
-    if (r0 >= r1 || c0 >= c1) return;
+    const int nblk = min(NBLK, (kend - kb + WNB - 1) / WNB);
+    const int ar = TileMap<T>::arow(i16);
     for (int cs = c0; cs < c1; cs += WCT) {
-        T uf[NT][S];
+        T uf[NT][S4];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int c = min(cs + 16 * t + i16, c1 - 1);
             const T *up = A + (size_t)c * ld + kb + k4;
 #pragma unroll
-            for (int s = 0; s < S; ++s) uf[t][s] = up[4 * s];
+            for (int s = 0; s < S4; ++s) uf[t][s] = (s < 4 * nblk) ? up[4 * s] : T(0);
         }
-        int ccol[NT][4];
+        // band solve, block by block
+#pragma unroll
+        for (int i = 0; i < NBLK; ++i) {
+            if (i < nblk) {
+                T li[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) li[s] = S.linv[slot0 + i][ar][4 * s + k4];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    acc_t acc;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[e] = T(0);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) acc = mfma_t(li[s], uf[t][4 * i + s], acc);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) uf[t][4 * i + e] = acc[e];
+                }
+#pragma unroll
+                for (int i2 = i + 1; i2 < NBLK; ++i2) {
+                    if (i2 < nblk) {
+                        T lf[4];   // -L[band block i2][band block i], rows permuted by arow
+                        const T *lp = A + (size_t)(kb + 16 * i + k4) * ld + kb + 16 * i2 + ar;
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) lf[s] = -lp[(size_t)(4 * s) * ld];
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) {
+                            acc_t acc;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) acc[e] = uf[t][4 * i2 + e];
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) acc = mfma_t(lf[s], uf[t][4 * i + s], acc);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) uf[t][4 * i2 + e] = acc[e];
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = cs + 16 * t + i16;
+            if (c < c1) {
+                T *up = A + (size_t)c * ld + kb + k4;
+#pragma unroll
+                for (int s = 0; s < S4; ++s)
+                    if (s < 4 * nblk) up[4 * s] = uf[t][s];
+            }
+        }
+        if (kend >= n) continue;
+
+        // trailing product A[kend:n, cs:cs+WCT) -= A[kend:n, band] U
+        size_t coff[NT][4];
+        bool cok[NT][4];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) ccol[t][e] = cs + 16 * t + TileMap<T>::col(lane, e);
-        for (int rt = r0; rt < r1; rt += 16) {
-            const int r = rt + i16;
-            const bool rok = r < r1;
-            const int rc = rok ? r : r1 - 1;
-            T lf[S];
-            const T *lp = A + (size_t)(kb + k4) * ld + rc;
+            for (int e = 0; e < 4; ++e) {
+                const int c = cs + 16 * t + TileMap<T>::col(lane, e);
+                cok[t][e] = c < c1;
+                coff[t][e] = (size_t)min(c, c1 - 1) * ld;
+            }
+        const T *lcol = A + (size_t)(kb + k4) * ld;
+        T lf[S4];
+        acc_t acc[NT], nxt[NT];
+        const int rc = min(kend + i16, n - 1);
 #pragma unroll
-            for (int s = 0; s < S; ++s) lf[s] = -lp[(size_t)(4 * s) * ld];
-            typename TileMap<T>::acc acc[NT];
+        for (int s = 0; s < S4; ++s) lf[s] = -lcol[(size_t)(4 * s) * ld + rc];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[t][e] = A[coff[t][e] + rc];
+        for (int rt = kend; rt < n; rt += 16) {
+            const int r = rt + i16;
+            const int rn = min(r + 16, n - 1);   // next tile's row (clamped)
 #pragma unroll
             for (int t = 0; t < NT; ++t)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) acc[t][e] = A[(size_t)min(ccol[t][e], c1 - 1) * ld + rc];
+                for (int e = 0; e < 4; ++e) nxt[t][e] = A[coff[t][e] + rn];
 #pragma unroll
-            for (int s = 0; s < S; ++s)
+            for (int s = 0; s < S4; ++s) {
 #pragma unroll
                 for (int t = 0; t < NT; ++t) acc[t] = mfma_t(uf[t][s], lf[s], acc[t]);
-            if (rok) {
+                lf[s] = -lcol[(size_t)(4 * s) * ld + rn];
+            }
+            if (r < n) {
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        if (ccol[t][e] < c1) A[(size_t)ccol[t][e] * ld + r] = acc[t][e];
+                        if (cok[t][e]) A[coff[t][e] + r] = acc[t][e];
             }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = nxt[t];
         }
     }
 }
@@ -232,7 +319,7 @@ __device__ __forceinline__ void wave_cols(T (&p)[R][WNB], int (&pos)[R], unsigne
 
 // ---- factor the panel of columns k0..k0+nb-1 (rows k0..n-1, R = rows/64) --
 template <typename T, int R>
-__device__ void wave_panel(T *A, int ld, int n, int k0, int nb, int32_t *piv, int &info, WaveLds<T> &S) {
+__device__ __forceinline__ void wave_panel(T *A, int ld, int n, int k0, int nb, int32_t *piv, int &info, WaveLds<T> &S) {
     const int lane = threadIdx.x;
     T p[R][WNB];
     int pos[R];
@@ -293,7 +380,7 @@ __device__ void wave_panel(T *A, int ld, int n, int k0, int nb, int32_t *piv, in
 
 // ---- apply the panel's row moves to every column outside it ----------------
 template <typename T>
-__device__ void wave_moves(T *A, int ld, int ncols, int k0, int nb, const WaveLds<T> &S) {
+__device__ __forceinline__ void wave_moves(T *A, int ld, int ncols, int k0, int nb, const WaveLds<T> &S) {
     const int nmv = __builtin_amdgcn_readfirstlane(S.nmv);
     if (nmv == 0) return;
     const int lane = threadIdx.x;
@@ -312,48 +399,53 @@ __device__ void wave_moves(T *A, int ld, int ncols, int k0, int nb, const WaveLd
     }
 }
 
-// ---- U12 = L11^{-1} A12 on rows k0..k0+15 of columns [c0, c1) ---------------
-// One lane per column; L11 (unit lower, zero outside the panel) from LDS.
-// Rows past n inside the 16 are zero padding and stay zero.
+// ---- inverse of the panel's unit-lower diagonal block: linv = l11^{-1} -----
+// Lane j < 16 solves L x = e_j by forward substitution (L from LDS).
 template <typename T>
-__device__ void wave_trsm(T *A, int ld, int k0, int c0, int c1, const WaveLds<T> &S) {
-    for (int c = c0 + (int)threadIdx.x; c < c1; c += WL) {
-        T *cp = A + (size_t)c * ld + k0;
-        T u[WNB];
+__device__ __forceinline__ void wave_linv(WaveLds<T> &S, int slot) {
+    const int lane = threadIdx.x;
+    if (lane < WNB) {
+        T x[WNB];
 #pragma unroll
-        for (int r = 0; r < WNB; ++r) u[r] = cp[r];
+        for (int r = 0; r < WNB; ++r) x[r] = (r == lane) ? T(1) : T(0);
 #pragma unroll
         for (int cc = 0; cc < WNB - 1; ++cc) {
-            const T uc = u[cc];
+            const T xc = x[cc];
 #pragma unroll
-            for (int r = cc + 1; r < WNB; ++r) u[r] -= S.l11[r][cc] * uc;
+            for (int r = cc + 1; r < WNB; ++r) x[r] -= S.l11[r][cc] * xc;
             // keep the scheduler from hoisting all 120 LDS reads of L11
             // ahead of the arithmetic (they would not fit in registers)
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int r = 0; r < WNB; ++r) cp[r] = u[r];
+        for (int r = 0; r < WNB; ++r) S.linv[slot][r][lane] = x[r];
     }
 }
 
 // ---- back substitution U x = y, y in LDS ------------------------------------
-// 64-row diagonal blocks from the bottom: lane = row, the solved entry of
-// each step broadcast through a scalar register; then the rows above take
-// the block's contribution.
+// 64-row diagonal blocks from the bottom: lane = row, with the lane's row of
+// the block loaded into registers up front (one round trip), and the solved
+// entry of each step broadcast through a scalar register; then the rows
+// above take the block's contribution.
 template <typename T>
-__device__ void wave_trsv_upper(const T *U, int ld, int n, T *y) {
+__device__ __forceinline__ void wave_trsv_upper(const T *U, int ld, int n, T *y) {
     const int lane = threadIdx.x;
     for (int rb = ((n - 1) / WL) * WL; rb >= 0; rb -= WL) {
         const int w = min(WL, n - rb);
         const bool in = lane < w;
         const int r = rb + (in ? lane : 0);
+        T ub[WL];
+#pragma unroll
+        for (int j = 0; j < WL; ++j) ub[j] = U[(size_t)(rb + min(j, w - 1)) * ld + r];
         T yi = in ? y[r] : T(0);
         const T dinv = in ? T(1) / U[(size_t)r * ld + r] : T(0);
-        for (int j = w - 1; j >= 0; --j) {
-            const T ucol = U[(size_t)(rb + j) * ld + r];
-            if (lane == j) yi *= dinv;
-            const T xj = readlane_t(yi, j);
-            if (lane < j) yi -= ucol * xj;
+#pragma unroll
+        for (int j = WL - 1; j >= 0; --j) {
+            if (j < w) {
+                if (lane == j) yi *= dinv;
+                const T xj = readlane_t(yi, j);
+                if (lane < j) yi -= ub[j] * xj;
+            }
         }
         if (in) y[r] = yi;
         __syncthreads();
@@ -361,6 +453,7 @@ __device__ void wave_trsv_upper(const T *U, int ld, int n, T *y) {
             const T *up = U + (size_t)rb * ld + rr;
             T s0 = y[rr], s1 = T(0);
             int j = 0;
+#pragma unroll 8
             for (; j + 1 < w; j += 2) {
                 s0 -= up[(size_t)j * ld] * y[rb + j];
                 s1 -= up[(size_t)(j + 1) * ld] * y[rb + j + 1];
@@ -412,36 +505,19 @@ __global__ __launch_bounds__(WL, 2) void lu_wave_kernel(WsView v, int32_t first,
                 panel_if<T, 5>(rows, A, ld, n, k0, nb, piv, info, S);
             __syncthreads();
             wave_moves<T>(A, ld, ncols, k0, nb, S);
+            wave_linv<T>(S, (k0 - K0) / WNB);
             __syncthreads();
-            const int c0 = k0 + nb;
-            if (c0 < kend) {
-                wave_trsm<T>(A, ld, k0, c0, kend, S);
-                __syncthreads();
-                wave_gemm<T, WNB>(A, ld, c0, n, c0, kend, k0);
+            // the panel's U rows and rank-16 update for the super-panel's
+            // remaining columns
+            if (k0 + nb < kend) {
+                wave_update<T, 1>(A, ld, n, k0, k0 + nb, k0 + nb, kend, S, (k0 - K0) / WNB);
                 __syncthreads();
             }
         }
+        // columns right of the super-panel: U12 rows and the rank-64 update
         if (kend < ncols) {
-            for (int kp = K0; kp < kend; kp += WNB) {
-                const int nbp = min(WNB, kend - kp);
-                if (lane < WNB) {
-                    const T *lrow = A + (size_t)kp * ld + kp + lane;
-#pragma unroll
-                    for (int cc = 0; cc < WNB; ++cc)
-                        S.l11[lane][cc] = (cc < lane && lane < nbp) ? lrow[(size_t)cc * ld] : T(0);
-                }
-                __syncthreads();
-                wave_trsm<T>(A, ld, kp, kend, ncols, S);
-                __syncthreads();
-                if (kp + WNB < kend) {
-                    wave_gemm<T, WNB>(A, ld, kp + WNB, kend, kend, ncols, kp);
-                    __syncthreads();
-                }
-            }
-            if (kend < n) {
-                wave_gemm<T, WSP>(A, ld, kend, n, kend, ncols, K0);
-                __syncthreads();
-            }
+            wave_update<T, WSP / WNB>(A, ld, n, K0, kend, kend, ncols, S, 0);
+            __syncthreads();
         }
     }
 
