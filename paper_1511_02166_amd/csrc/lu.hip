@@ -532,7 +532,7 @@ __global__ __launch_bounds__(TPB, 2) void lu_kernel(WsView v, int32_t *__restric
 // x += d, and stop once ||d||_inf <= tol ||x||_inf.
 __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restrict__ info, double tol,
                                                      int max_iter) {
-    const int b = blockIdx.x;
+    const int b = v.order[blockIdx.x];
     const AirfoilMeta mt = v.meta[b];
     const int n = mt.n1, ld = mt.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -679,8 +679,15 @@ hipError_t launch_factor_solve(const WsView &v, int32_t B, int32_t n_block, int3
     }
     e = launch_lu_wave(v, n_block, B - n_block, mixed, info, stream);
     if (e != hipSuccess) return e;
-    if (mixed) refine_kernel<<<B, TPB, 0, stream>>>(v, info, tol, max_iter);
-    return hipGetLastError();
+    if (mixed) {
+        if (n_block > 0) {
+            refine_kernel<<<n_block, TPB, 0, stream>>>(v, info, tol, max_iter);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        e = launch_refine_wave(v, n_block, B - n_block, info, tol, max_iter, stream);
+    }
+    return e;
 }
 
 }  // namespace panel

@@ -40,7 +40,11 @@ namespace {
 
 constexpr int WL = 64;    // lanes: one wavefront per airfoil
 constexpr int WSP = 64;   // super-panel width (rank of the trailing update)
-constexpr int WCT = 32;   // trailing columns whose U fragments are held at once
+// trailing columns whose U fragments are held in registers at once (as many
+// as fit in the register budget without spilling)
+template <typename T> struct Wct;
+template <> struct Wct<double> { static constexpr int v = 32; };
+template <> struct Wct<float> { static constexpr int v = 48; };
 constexpr int WNB = 16;   // pivot panel width
 
 typedef double d4w_t __attribute__((ext_vector_type(4)));
@@ -118,6 +122,7 @@ template <typename T, int NBLK>
 __device__ __forceinline__ void wave_update(T *A, int ld, int n, int kb, int kend, int c0, int c1,
                                             const WaveLds<T> &S, int slot0) {
     constexpr int S4 = 4 * NBLK;   // k-steps (4 rows each) of the band
+    constexpr int WCT = Wct<T>::v;
     constexpr int NT = WCT / 16;
     typedef typename TileMap<T>::acc acc_t;
     const int lane = threadIdx.x, i16 = lane & 15, k4 = lane >> 4;
@@ -538,6 +543,173 @@ __global__ __launch_bounds__(WL, 2) void lu_wave_kernel(WsView v, int32_t first,
     }
 }
 
+// ---- forward substitution L y = y (unit lower), y in LDS --------------------
+// Same blocking as the back substitution, top down.
+template <typename T>
+__device__ __forceinline__ void wave_trsv_lower_unit(const T *L, int ld, int n, T *y) {
+    const int lane = threadIdx.x;
+    for (int rb = 0; rb < n; rb += WL) {
+        const int w = min(WL, n - rb);
+        const bool in = lane < w;
+        const int r = rb + (in ? lane : 0);
+        T lb[WL];
+#pragma unroll
+        for (int j = 0; j < WL; ++j) lb[j] = L[(size_t)(rb + min(j, w - 1)) * ld + r];
+        T yi = in ? y[r] : T(0);
+#pragma unroll
+        for (int j = 0; j < WL; ++j) {
+            if (j < w) {
+                const T xj = readlane_t(yi, j);
+                if (lane > j) yi -= lb[j] * xj;
+            }
+        }
+        if (in) y[r] = yi;
+        __syncthreads();
+        for (int rr = rb + w + lane; rr < n; rr += WL) {
+            // rows below a block exist only when the block is full (w == 64)
+            const T *lp = L + (size_t)rb * ld + rr;
+            T s0 = y[rr], s1 = T(0);
+#pragma unroll 8
+            for (int j = 0; j < WL; j += 2) {
+                s0 -= lp[(size_t)j * ld] * y[rb + j];
+                s1 -= lp[(size_t)(j + 1) * ld] * y[rb + j + 1];
+            }
+            y[rr] = s0 + s1;
+        }
+        __syncthreads();
+    }
+}
+
+// Largest value over the wavefront of three per-lane values.
+__device__ __forceinline__ void wave_max3(double &a, double &b, double &c) {
+    a = wave_max(a);
+    b = wave_max(b);
+    c = wave_max(c);
+}
+
+// ---- mixed precision: iterative refinement, one wavefront per airfoil -------
+// X holds the solution from the FP32 factors; A64 the FP64 system; A32 the
+// FP32 factors and piv the pivots.  One sweep: r = b - A x in FP64 (rows held
+// by lanes, the matrix streamed column by column); stop if r is at the FP64
+// backward-error floor, ||r||_inf <= sqrt(n) eps ||A||_inf ||x||_inf (no
+// further sweep can improve x); otherwise d = U^{-1} L^{-1} P r in FP32,
+// x += d, and stop once ||d||_inf <= tol ||x||_inf.
+__global__ __launch_bounds__(WL) void refine_wave_kernel(WsView v, int32_t first, int32_t *__restrict__ info,
+                                                         double tol, int max_iter) {
+    constexpr int RM = PANEL_WAVE_RMAX;
+    const int b = v.order[first + blockIdx.x];
+    const AirfoilMeta mt = v.meta[b];
+    const int n = mt.n1, ld = mt.ld;
+    const int lane = threadIdx.x;
+    if (info[b] != 0) {
+        if (lane == 0) {
+            v.iters[b] = 0;
+            v.flag[b] = info[b];
+        }
+        return;
+    }
+    const double *A = v.a64 + mt.a_off;
+    const float *LU = v.a32 + mt.a_off;
+    const int32_t *piv = v.piv + mt.piv_off;
+    double *X = v.x + mt.x_off;
+    __shared__ double sx[WL * RM];
+    __shared__ double sr[WL * RM];
+    __shared__ float sd[WL * RM];
+    __shared__ int perm[WL * RM];
+    if (lane == 0) {
+        for (int i = 0; i < n; ++i) perm[i] = i;
+        for (int i = 0; i < n; ++i) {
+            const int p = piv[i];
+            const int t0 = perm[i];
+            perm[i] = perm[p];
+            perm[p] = t0;
+        }
+    }
+    const double floor_c = sqrt((double)n) * 2.220446049250313e-16;
+    double anrm = -1.0;   // ||A||_inf, found during the first residual
+    int worst = 0;
+    bool failed = max_iter == 0;
+    for (int k = 0; k < mt.K; ++k) {
+        for (int i = lane; i < n; i += WL) sx[i] = X[(size_t)k * n + i];
+        __syncthreads();
+        bool conv = false;
+        int sweeps = 0;
+        for (int it = 0; it < max_iter && !conv; ++it) {
+            // residual, lane owns rows lane + 64 q
+            double rs[RM], ra[RM];
+#pragma unroll
+            for (int q = 0; q < RM; ++q) {
+                const int r = min(lane + WL * q, n - 1);
+                rs[q] = A[(size_t)(n + k) * ld + r];
+                ra[q] = 0.0;
+            }
+            if (anrm < 0.0) {
+                for (int j = 0; j < n; ++j) {
+                    const double xj = sx[j];
+                    const double *col = A + (size_t)j * ld + lane;
+#pragma unroll
+                    for (int q = 0; q < RM; ++q) {
+                        const double a = col[min(WL * q, n - 1 - lane)];
+                        rs[q] -= a * xj;
+                        ra[q] += fabs(a);
+                    }
+                }
+            } else {
+#pragma unroll 4
+                for (int j = 0; j < n; ++j) {
+                    const double xj = sx[j];
+                    const double *col = A + (size_t)j * ld + lane;
+#pragma unroll
+                    for (int q = 0; q < RM; ++q) rs[q] -= col[min(WL * q, n - 1 - lane)] * xj;
+                }
+            }
+            double rmax = 0.0, xmax = 0.0, rowmax = 0.0;
+#pragma unroll
+            for (int q = 0; q < RM; ++q) {
+                const int r = lane + WL * q;
+                if (r < n) {
+                    sr[r] = rs[q];
+                    rmax = fmax(rmax, fabs(rs[q]));
+                    xmax = fmax(xmax, fabs(sx[r]));
+                    rowmax = fmax(rowmax, ra[q]);
+                }
+            }
+            wave_max3(rmax, xmax, rowmax);
+            if (anrm < 0.0) anrm = rowmax;
+            if (rmax <= floor_c * anrm * xmax) {
+                conv = true;
+                break;
+            }
+            __syncthreads();
+            for (int i = lane; i < n; i += WL) sd[i] = (float)sr[perm[i]];
+            __syncthreads();
+            wave_trsv_lower_unit<float>(LU, ld, n, sd);
+            wave_trsv_upper<float>(LU, ld, n, sd);
+            double dmax = 0.0, xn = 0.0, unused = 0.0;
+            for (int i = lane; i < n; i += WL) {
+                const double d = (double)sd[i];
+                const double x1 = sx[i] + d;
+                sx[i] = x1;
+                dmax = fmax(dmax, fabs(d));
+                xn = fmax(xn, fabs(x1));
+            }
+            wave_max3(dmax, xn, unused);
+            __syncthreads();
+            ++sweeps;
+            conv = dmax <= tol * xn;
+        }
+        if (!conv) failed = true;
+        worst = max(worst, sweeps);
+        for (int i = lane; i < n; i += WL) X[(size_t)k * n + i] = sx[i];
+        __syncthreads();
+    }
+    if (lane == 0) {
+        v.iters[b] = worst;
+        if (failed) info[b] = -2;
+        v.flag[b] = info[b];
+    }
+}
+
 }  // namespace
 
 hipError_t launch_lu_wave(const WsView &v, int32_t first, int32_t count, int32_t mixed, int32_t *info,
@@ -547,6 +719,13 @@ hipError_t launch_lu_wave(const WsView &v, int32_t first, int32_t count, int32_t
         lu_wave_kernel<float><<<count, WL, 0, stream>>>(v, first, info);
     else
         lu_wave_kernel<double><<<count, WL, 0, stream>>>(v, first, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_wave(const WsView &v, int32_t first, int32_t count, int32_t *info, double tol,
+                              int32_t max_iter, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    refine_wave_kernel<<<count, WL, 0, stream>>>(v, first, info, tol, max_iter);
     return hipGetLastError();
 }
 

@@ -99,6 +99,8 @@ hipError_t launch_factor_solve(const WsView &v, int32_t B, int32_t n_block, int3
                                hipStream_t stream);
 hipError_t launch_lu_wave(const WsView &v, int32_t first, int32_t count, int32_t mixed, int32_t *info,
                           hipStream_t stream);
+hipError_t launch_refine_wave(const WsView &v, int32_t first, int32_t count, int32_t *info, double tol,
+                              int32_t max_iter, hipStream_t stream);
 hipError_t launch_forces(const WsView &v, int32_t B, int32_t max_k, double *gamma, double *cp,
                          double *cl, double *cl_p, hipStream_t stream);
 hipError_t launch_math_eval(int32_t n, const double *x, const double *y, double *lg, double *at,
