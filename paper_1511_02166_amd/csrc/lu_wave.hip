@@ -118,87 +118,128 @@ template <typename T> struct WaveLds {
 // fragment into the register the current product has just consumed).  Rows
 // past n / columns past c1 are clamped for the loads and never stored; rows
 // of the band past n are zero padding (linv is the identity there).
-template <typename T, int NBLK>
-__device__ __forceinline__ void wave_update(T *A, int ld, int n, int kb, int kend, int c0, int c1,
-                                            const WaveLds<T> &S, int slot0) {
+// One chunk of NT 16-column tiles starting at column cs (columns past c1
+// are clamped for the loads and never stored).
+template <typename T, int NBLK, int NT>
+__device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int kend, int cs, int c1,
+                                             const WaveLds<T> &S, int slot0, int nblk) {
     constexpr int S4 = 4 * NBLK;   // k-steps (4 rows each) of the band
-    constexpr int WCT = Wct<T>::v;
-    constexpr int NT = WCT / 16;
     typedef typename TileMap<T>::acc acc_t;
     const int lane = threadIdx.x, i16 = lane & 15, k4 = lane >> 4;
-    const int nblk = min(NBLK, (kend - kb + WNB - 1) / WNB);
     const int ar = TileMap<T>::arow(i16);
-    for (int cs = c0; cs < c1; cs += WCT) {
-        T uf[NT][S4];
+    T uf[NT][S4];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int c = min(cs + 16 * t + i16, c1 - 1);
-            const T *up = A + (size_t)c * ld + kb + k4;
+    for (int t = 0; t < NT; ++t) {
+        const int c = min(cs + 16 * t + i16, c1 - 1);
+        const T *up = A + (size_t)c * ld + kb + k4;
 #pragma unroll
-            for (int s = 0; s < S4; ++s) uf[t][s] = (s < 4 * nblk) ? up[4 * s] : T(0);
-        }
-        // band solve, block by block
+        for (int s = 0; s < S4; ++s) uf[t][s] = (s < 4 * nblk) ? up[4 * s] : T(0);
+    }
+    // band solve, block by block
 #pragma unroll
-        for (int i = 0; i < NBLK; ++i) {
-            if (i < nblk) {
-                T li[4];
+    for (int i = 0; i < NBLK; ++i) {
+        if (i < nblk) {
+            T li[4];
 #pragma unroll
-                for (int s = 0; s < 4; ++s) li[s] = S.linv[slot0 + i][ar][4 * s + k4];
+            for (int s = 0; s < 4; ++s) li[s] = S.linv[slot0 + i][ar][4 * s + k4];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    acc_t acc;
+            for (int t = 0; t < NT; ++t) {
+                acc_t acc;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) acc[e] = T(0);
+                for (int e = 0; e < 4; ++e) acc[e] = T(0);
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) acc = mfma_t(li[s], uf[t][4 * i + s], acc);
+                for (int s = 0; s < 4; ++s) acc = mfma_t(li[s], uf[t][4 * i + s], acc);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) uf[t][4 * i + e] = acc[e];
-                }
+                for (int e = 0; e < 4; ++e) uf[t][4 * i + e] = acc[e];
+            }
 #pragma unroll
-                for (int i2 = i + 1; i2 < NBLK; ++i2) {
-                    if (i2 < nblk) {
-                        T lf[4];   // -L[band block i2][band block i], rows permuted by arow
-                        const T *lp = A + (size_t)(kb + 16 * i + k4) * ld + kb + 16 * i2 + ar;
+            for (int i2 = i + 1; i2 < NBLK; ++i2) {
+                if (i2 < nblk) {
+                    T lf[4];   // -L[band block i2][band block i], rows permuted by arow
+                    const T *lp = A + (size_t)(kb + 16 * i + k4) * ld + kb + 16 * i2 + ar;
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) lf[s] = -lp[(size_t)(4 * s) * ld];
+                    for (int s = 0; s < 4; ++s) lf[s] = -lp[(size_t)(4 * s) * ld];
 #pragma unroll
-                        for (int t = 0; t < NT; ++t) {
-                            acc_t acc;
+                    for (int t = 0; t < NT; ++t) {
+                        acc_t acc;
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) acc[e] = uf[t][4 * i2 + e];
+                        for (int e = 0; e < 4; ++e) acc[e] = uf[t][4 * i2 + e];
 #pragma unroll
-                            for (int s = 0; s < 4; ++s) acc = mfma_t(lf[s], uf[t][4 * i + s], acc);
+                        for (int s = 0; s < 4; ++s) acc = mfma_t(lf[s], uf[t][4 * i + s], acc);
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) uf[t][4 * i2 + e] = acc[e];
-                        }
+                        for (int e = 0; e < 4; ++e) uf[t][4 * i2 + e] = acc[e];
                     }
                 }
             }
         }
+    }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int c = cs + 16 * t + i16;
-            if (c < c1) {
-                T *up = A + (size_t)c * ld + kb + k4;
+    for (int t = 0; t < NT; ++t) {
+        const int c = cs + 16 * t + i16;
+        if (c < c1) {
+            T *up = A + (size_t)c * ld + kb + k4;
 #pragma unroll
-                for (int s = 0; s < S4; ++s)
-                    if (s < 4 * nblk) up[4 * s] = uf[t][s];
+            for (int s = 0; s < S4; ++s)
+                if (s < 4 * nblk) up[4 * s] = uf[t][s];
+        }
+    }
+    if (kend >= n) return;
+
+    // trailing product A[kend:n, cs:cs+16NT) -= A[kend:n, band] U
+    int coff[NT][4];   // element offsets of this lane's C columns (clamped)
+    bool cok[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = cs + 16 * t + TileMap<T>::col(lane, e);
+            cok[t][e] = c < c1;
+            coff[t][e] = min(c, c1 - 1) * ld;
+        }
+    const T *lcol = A + (size_t)(kb + k4) * ld;
+    if constexpr (NBLK == 1) {
+        // little work per tile (8 products): D tiles in flight; each step
+        // computes one tile and issues the loads of the tile D - 1 ahead
+        // into the slot just freed
+        constexpr int D = 4;
+        T lf[D][S4];
+        acc_t acc[D][NT];
+        auto load_tile = [&](int slot, int rt) {
+            const int rr = min(rt + i16, n - 1);
+#pragma unroll
+            for (int s = 0; s < S4; ++s) lf[slot][s] = -lcol[(size_t)(4 * s) * ld + rr];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[slot][t][e] = A[coff[t][e] + rr];
+        };
+#pragma unroll
+        for (int d = 0; d < D - 1; ++d) load_tile(d, kend + 16 * d);
+        for (int rt = kend; rt < n; rt += 16 * D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int r0 = rt + 16 * d;
+                load_tile((d + D - 1) % D, r0 + 16 * (D - 1));
+                if (r0 < n) {
+#pragma unroll
+                    for (int s = 0; s < S4; ++s)
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) acc[d][t] = mfma_t(uf[t][s], lf[d][s], acc[d][t]);
+                    const int r = r0 + i16;
+                    if (r < n) {
+#pragma unroll
+                        for (int t = 0; t < NT; ++t)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (cok[t][e]) A[coff[t][e] + r] = acc[d][t][e];
+                    }
+                }
             }
         }
-        if (kend >= n) continue;
-
-        // trailing product A[kend:n, cs:cs+WCT) -= A[kend:n, band] U
-        size_t coff[NT][4];
-        bool cok[NT][4];
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int c = cs + 16 * t + TileMap<T>::col(lane, e);
-                cok[t][e] = c < c1;
-                coff[t][e] = (size_t)min(c, c1 - 1) * ld;
-            }
-        const T *lcol = A + (size_t)(kb + k4) * ld;
+    } else {
+        // 16 x 16NT x 64 per tile: the next tile's C block goes into a second
+        // accumulator set at the start, each of its L fragments into the
+        // register the current product has just consumed
         T lf[S4];
         acc_t acc[NT], nxt[NT];
         const int rc = min(kend + i16, n - 1);
@@ -232,6 +273,25 @@ __device__ __forceinline__ void wave_update(T *A, int ld, int n, int kb, int ken
             for (int t = 0; t < NT; ++t) acc[t] = nxt[t];
         }
     }
+}
+
+template <typename T, int NBLK>
+__device__ __forceinline__ void wave_update(T *A, int ld, int n, int kb, int kend, int c0, int c1,
+                                            const WaveLds<T> &S, int slot0) {
+    constexpr int NTM = Wct<T>::v / 16;
+    const int nblk = min(NBLK, (kend - kb + WNB - 1) / WNB);
+    // full chunks, then a narrower one for the remainder (a trailing block
+    // of n1 + K columns is rarely a multiple of the chunk width)
+    int cs = c0;
+    for (; c1 - cs > 16 * (NTM - 1); cs += 16 * NTM)
+        update_chunk<T, NBLK, NTM>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
+    if constexpr (NTM > 2) {
+        if (c1 - cs > 16) {
+            update_chunk<T, NBLK, 2>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
+            cs += 32;
+        }
+    }
+    if (cs < c1) update_chunk<T, NBLK, 1>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
 }
 
 // ---- one column step of the panel factorisation (C is compile-time) --------
@@ -432,7 +492,7 @@ __device__ __forceinline__ void wave_linv(WaveLds<T> &S, int slot) {
 // the block loaded into registers up front (one round trip), and the solved
 // entry of each step broadcast through a scalar register; then the rows
 // above take the block's contribution.
-template <typename T>
+template <typename T, bool BATCH>
 __device__ __forceinline__ void wave_trsv_upper(const T *U, int ld, int n, T *y) {
     const int lane = threadIdx.x;
     for (int rb = ((n - 1) / WL) * WL; rb >= 0; rb -= WL) {
@@ -457,13 +517,26 @@ __device__ __forceinline__ void wave_trsv_upper(const T *U, int ld, int n, T *y)
         for (int rr = lane; rr < rb; rr += WL) {
             const T *up = U + (size_t)rb * ld + rr;
             T s0 = y[rr], s1 = T(0);
-            int j = 0;
+            if constexpr (BATCH) {
+                // the row's 64 entries of the block in one round trip
+#pragma unroll
+                for (int j = 0; j < WL; ++j) ub[j] = up[(size_t)min(j, w - 1) * ld];
+#pragma unroll
+                for (int j = 0; j < WL; j += 2) {
+                    const T x0 = (j < w) ? y[rb + j] : T(0);
+                    const T x1 = (j + 1 < w) ? y[rb + j + 1] : T(0);
+                    s0 -= ub[j] * x0;
+                    s1 -= ub[j + 1] * x1;
+                }
+            } else {
+                int j = 0;
 #pragma unroll 8
-            for (; j + 1 < w; j += 2) {
-                s0 -= up[(size_t)j * ld] * y[rb + j];
-                s1 -= up[(size_t)(j + 1) * ld] * y[rb + j + 1];
+                for (; j + 1 < w; j += 2) {
+                    s0 -= up[(size_t)j * ld] * y[rb + j];
+                    s1 -= up[(size_t)(j + 1) * ld] * y[rb + j + 1];
+                }
+                if (j < w) s0 -= up[(size_t)j * ld] * y[rb + j];
             }
-            if (j < w) s0 -= up[(size_t)j * ld] * y[rb + j];
             y[rr] = s0 + s1;
         }
         __syncthreads();
@@ -537,7 +610,7 @@ __global__ __launch_bounds__(WL, 2) void lu_wave_kernel(WsView v, int32_t first,
     for (int k = 0; k < mt.K; ++k) {
         for (int i = lane; i < n; i += WL) y[i] = A[(size_t)(n + k) * ld + i];
         __syncthreads();
-        wave_trsv_upper<T>(A, ld, n, y);
+        wave_trsv_upper<T, true>(A, ld, n, y);
         for (int i = lane; i < n; i += WL) X[(size_t)k * n + i] = (double)y[i];
         __syncthreads();
     }
@@ -594,7 +667,7 @@ __device__ __forceinline__ void wave_max3(double &a, double &b, double &c) {
 // backward-error floor, ||r||_inf <= sqrt(n) eps ||A||_inf ||x||_inf (no
 // further sweep can improve x); otherwise d = U^{-1} L^{-1} P r in FP32,
 // x += d, and stop once ||d||_inf <= tol ||x||_inf.
-__global__ __launch_bounds__(WL) void refine_wave_kernel(WsView v, int32_t first, int32_t *__restrict__ info,
+__global__ __launch_bounds__(WL, 2) void refine_wave_kernel(WsView v, int32_t first, int32_t *__restrict__ info,
                                                          double tol, int max_iter) {
     constexpr int RM = PANEL_WAVE_RMAX;
     const int b = v.order[first + blockIdx.x];
@@ -684,7 +757,7 @@ __global__ __launch_bounds__(WL) void refine_wave_kernel(WsView v, int32_t first
             for (int i = lane; i < n; i += WL) sd[i] = (float)sr[perm[i]];
             __syncthreads();
             wave_trsv_lower_unit<float>(LU, ld, n, sd);
-            wave_trsv_upper<float>(LU, ld, n, sd);
+            wave_trsv_upper<float, false>(LU, ld, n, sd);
             double dmax = 0.0, xn = 0.0, unused = 0.0;
             for (int i = lane; i < n; i += WL) {
                 const double d = (double)sd[i];
