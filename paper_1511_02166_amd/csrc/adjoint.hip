@@ -136,7 +136,7 @@ template <typename T>
 __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__restrict__ xy,
                                                       const double *__restrict__ dcl,
                                                       double *__restrict__ dxy) {
-    const int b = blockIdx.x;
+    const int b = v.order[blockIdx.x];
     const AirfoilMeta mt = v.meta[b];
     const int N = mt.N, n1 = mt.n1, K = mt.K, ld = mt.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -378,13 +378,17 @@ __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__
 
 }  // namespace
 
-hipError_t launch_adjoint(const WsView &v, int32_t B, int32_t, int32_t mixed, const double *xy,
+hipError_t launch_adjoint(const WsView &v, int32_t B, int32_t n_block, int32_t mixed, const double *xy,
                           const double *dcl, double *dxy, hipStream_t stream) {
-    if (mixed)
-        adjoint_kernel<float><<<B, TPB, 0, stream>>>(v, xy, dcl, dxy);
-    else
-        adjoint_kernel<double><<<B, TPB, 0, stream>>>(v, xy, dcl, dxy);
-    return hipGetLastError();
+    if (n_block > 0) {
+        if (mixed)
+            adjoint_kernel<float><<<n_block, TPB, 0, stream>>>(v, xy, dcl, dxy);
+        else
+            adjoint_kernel<double><<<n_block, TPB, 0, stream>>>(v, xy, dcl, dxy);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return launch_adjoint_wave(v, n_block, B - n_block, mixed, xy, dcl, dxy, stream);
 }
 
 }  // namespace panel

@@ -298,7 +298,7 @@ panel_status panel_adjoint(const panel_plan *plan, const void *ws, const double 
     if (!aligned8(xy) || !aligned8(dcl) || !aligned8(dxy))
         return fail(PANEL_EINVAL, "arrays must be 8-byte aligned");
     WsView v = ws_view(const_cast<void *>(ws), plan->layout);
-    hipError_t e = launch_adjoint(v, plan->B, plan->max_n1, plan->precision == PANEL_FP32_REFINE, xy,
+    hipError_t e = launch_adjoint(v, plan->B, plan->n_block, plan->precision == PANEL_FP32_REFINE, xy,
                                   dcl, dxy, static_cast<hipStream_t>(stream));
     return check_hip(e, "adjoint launch");
 }

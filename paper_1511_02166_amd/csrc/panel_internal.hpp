@@ -105,7 +105,9 @@ hipError_t launch_forces(const WsView &v, int32_t B, int32_t max_k, double *gamm
                          double *cl, double *cl_p, hipStream_t stream);
 hipError_t launch_math_eval(int32_t n, const double *x, const double *y, double *lg, double *at,
                             hipStream_t stream);
-hipError_t launch_adjoint(const WsView &v, int32_t B, int32_t max_n1, int32_t mixed,
+hipError_t launch_adjoint(const WsView &v, int32_t B, int32_t n_block, int32_t mixed,
                           const double *xy, const double *dcl, double *dxy, hipStream_t stream);
+hipError_t launch_adjoint_wave(const WsView &v, int32_t first, int32_t count, int32_t mixed, const double *xy,
+                               const double *dcl, double *dxy, hipStream_t stream);
 
 }  // namespace panel
