@@ -38,8 +38,8 @@ ASM_FLOPS_PER_ENTRY = 118.0
 # HBM bytes moved by one launch of the FP64 LU kernel on the 2048 x N=256
 # batch, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's
 # readings (x2.0 and x1.0).  Valid only for the kernel source it was taken
-# on, which is identified by the SHA-256 prefix of csrc/lu.hip.
-LU_TRAFFIC = {"96db77a830f2ad44": 9_070_497_848}
+# on, which is identified by the SHA-256 prefix of that source file.
+LU_TRAFFIC = {("lu_wave.hip", "6ee0c49e782c9206"): 11_080_358_112}   # one wavefront per airfoil
 
 
 def _args():
@@ -179,10 +179,11 @@ def main():
     dom = "lu_solve_f64" if lu_ms >= asm_ms else "assemble_f64"
     roof = dict(kern[dom])
     traffic = None
-    if dom == "lu_solve_f64" and a.config == 2 and a.batch is None:
+    if dom == "lu_solve_f64" and a.config == 2 and a.batch is None and a.wave_limit is None:
         import hashlib
-        with open(os.path.join(os.path.dirname(P.__file__), "csrc", "lu.hip"), "rb") as f:
-            traffic = LU_TRAFFIC.get(hashlib.sha256(f.read()).hexdigest()[:16])
+        src = "lu_wave.hip"
+        with open(os.path.join(os.path.dirname(P.__file__), "csrc", src), "rb") as f:
+            traffic = LU_TRAFFIC.get((src, hashlib.sha256(f.read()).hexdigest()[:16]))
     roof = {"kernel": dom, "bound": roof["bound"], "achieved": roof["achieved"], "peak": roof["peak"],
             "unit": roof["unit"], "frac": roof["frac"], "traffic": traffic}
 

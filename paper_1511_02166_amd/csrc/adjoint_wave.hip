@@ -266,6 +266,7 @@ __global__ __launch_bounds__(WL, 2) void adjoint_wave_kernel(WsView v, int32_t f
         double pbx = 0.0, pby = 0.0, psx = 0.0, psy = 0.0;
 #pragma unroll
         for (int q = 0; q < RM; ++q) {
+            if (q * WL >= N) break;   // slots past the last control point (uniform)
             const double e2x = mx[q] - Bx, e2y = my[q] - By;
             const double l2 = plog(e2x * e2x + e2y * e2y);
             const double cr = d1x[q] * e2y - d1y[q] * e2x;
