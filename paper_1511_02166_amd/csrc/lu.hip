@@ -526,12 +526,15 @@ __global__ __launch_bounds__(TPB, 2) void lu_kernel(WsView v, int32_t *__restric
 }
 
 // Mixed precision: iterative refinement of X with the FP64 system in A64 and
-// the FP32 factors in A32.  One sweep: r = b - A x in FP64; stop if r is at
-// the FP64 backward-error floor, ||r||_inf <= sqrt(n) eps ||A||_inf ||x||_inf
-// (no further sweep can improve x); otherwise d = U^{-1} L^{-1} P r in FP32,
-// x += d, and stop once ||d||_inf <= tol ||x||_inf.
+// the FP32 factors in A32.  One sweep: r = b - A x in FP64 (one pass over A
+// serving KG right-hand sides); for each right-hand side not yet converged:
+// stop if r is at the FP64 backward-error floor, ||r||_inf <= sqrt(n) eps
+// ||A||_inf ||x||_inf (no further sweep can improve x); otherwise
+// d = U^{-1} L^{-1} P r in FP32, x += d, and stop once ||d||_inf <= tol
+// ||x||_inf.
 __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restrict__ info, double tol,
                                                      int max_iter) {
+    constexpr int KG = 2;
     const int b = v.order[blockIdx.x];
     const AirfoilMeta mt = v.meta[b];
     const int n = mt.n1, ld = mt.ld;
@@ -547,8 +550,8 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
     const float *LU = v.a32 + mt.a_off;
     const int32_t *piv = v.piv + mt.piv_off;
     double *X = v.x + mt.x_off;
-    __shared__ double sx[PANEL_NMAX + 1];
-    __shared__ double sr[PANEL_NMAX + 1];
+    __shared__ double sx[KG][PANEL_NMAX + 1];
+    __shared__ double sr[KG][PANEL_NMAX + 1];
     __shared__ float sd[PANEL_NMAX + 1];
     __shared__ int perm[PANEL_NMAX + 1];
     __shared__ double red[3][TPB / 64];
@@ -589,55 +592,91 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
     double anrm = -1.0;   // ||A||_inf, found during the first residual
     int worst = 0;
     bool failed = max_iter == 0;
-    for (int k = 0; k < mt.K; ++k) {
-        for (int i = tid; i < n; i += TPB) sx[i] = X[(size_t)k * n + i];
+    for (int k0 = 0; k0 < mt.K; k0 += KG) {
+        const int kn = min(KG, mt.K - k0);
+        for (int kk = 0; kk < kn; ++kk)
+            for (int i = tid; i < n; i += TPB) sx[kk][i] = X[(size_t)(k0 + kk) * n + i];
         __syncthreads();
-        bool conv = false;
-        int sweeps = 0;
-        for (int it = 0; it < max_iter && !conv; ++it) {
-            double rmax = 0.0, xmax = 0.0, rowmax = 0.0;
+        bool conv[KG];
+        int sweeps[KG];
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) {
+            conv[kk] = kk >= kn;
+            sweeps[kk] = 0;
+        }
+        for (int it = 0; it < max_iter; ++it) {
+            bool all = true;
+#pragma unroll
+            for (int kk = 0; kk < KG; ++kk) all = all && conv[kk];
+            if (all) break;
+            double rowmax = 0.0;
             for (int i = tid; i < n; i += TPB) {
-                double s = A[(size_t)(n + k) * ld + i];
+                double s0 = A[(size_t)(n + k0) * ld + i];
+                double s1 = (kn > 1) ? A[(size_t)(n + k0 + 1) * ld + i] : 0.0;
                 double ra = 0.0;
                 if (anrm < 0.0) {
                     for (int j = 0; j < n; ++j) {
                         const double a = A[(size_t)j * ld + i];
-                        s -= a * sx[j];
+                        s0 -= a * sx[0][j];
+                        s1 -= a * sx[1][j];
                         ra += fabs(a);
                     }
+                } else if (kn == 1) {
+                    for (int j = 0; j < n; ++j) s0 -= A[(size_t)j * ld + i] * sx[0][j];
                 } else {
-                    for (int j = 0; j < n; ++j) s -= A[(size_t)j * ld + i] * sx[j];
+                    for (int j = 0; j < n; ++j) {
+                        const double a = A[(size_t)j * ld + i];
+                        s0 -= a * sx[0][j];
+                        s1 -= a * sx[1][j];
+                    }
                 }
-                sr[i] = s;
-                rmax = fmax(rmax, fabs(s));
-                xmax = fmax(xmax, fabs(sx[i]));
+                sr[0][i] = s0;
+                sr[1][i] = s1;
                 rowmax = fmax(rowmax, ra);
             }
-            bmax3(rmax, xmax, rowmax);
-            if (anrm < 0.0) anrm = rowmax;
-            if (rmax <= floor_c * anrm * xmax) {
-                conv = true;
-                break;
+            if (anrm < 0.0) {
+                double u0 = 0.0, u1 = 0.0;
+                bmax3(rowmax, u0, u1);
+                anrm = rowmax;
             }
-            for (int i = tid; i < n; i += TPB) sd[i] = (float)sr[perm[i]];
             __syncthreads();
-            trsv_lower_unit<float, float>(LU, ld, n, sd, sblk);
-            trsv_upper<float, float>(LU, ld, n, sd, sblk);
-            double dmax = 0.0, xn = 0.0, unused = 0.0;
-            for (int i = tid; i < n; i += TPB) {
-                const double d = (double)sd[i];
-                const double x1 = sx[i] + d;
-                sx[i] = x1;
-                dmax = fmax(dmax, fabs(d));
-                xn = fmax(xn, fabs(x1));
+#pragma unroll
+            for (int kk = 0; kk < KG; ++kk) {
+                if (conv[kk]) continue;
+                double rmax = 0.0, xmax = 0.0, unused = 0.0;
+                for (int i = tid; i < n; i += TPB) {
+                    rmax = fmax(rmax, fabs(sr[kk][i]));
+                    xmax = fmax(xmax, fabs(sx[kk][i]));
+                }
+                bmax3(rmax, xmax, unused);
+                if (rmax <= floor_c * anrm * xmax) {
+                    conv[kk] = true;
+                    continue;
+                }
+                for (int i = tid; i < n; i += TPB) sd[i] = (float)sr[kk][perm[i]];
+                __syncthreads();
+                trsv_lower_unit<float, float>(LU, ld, n, sd, sblk);
+                trsv_upper<float, float>(LU, ld, n, sd, sblk);
+                double dmax = 0.0, xn = 0.0;
+                for (int i = tid; i < n; i += TPB) {
+                    const double d = (double)sd[i];
+                    const double x1 = sx[kk][i] + d;
+                    sx[kk][i] = x1;
+                    dmax = fmax(dmax, fabs(d));
+                    xn = fmax(xn, fabs(x1));
+                }
+                bmax3(dmax, xn, unused);
+                ++sweeps[kk];
+                conv[kk] = dmax <= tol * xn;
             }
-            bmax3(dmax, xn, unused);
-            ++sweeps;
-            conv = dmax <= tol * xn;
         }
-        if (!conv) failed = true;
-        worst = max(worst, sweeps);
-        for (int i = tid; i < n; i += TPB) X[(size_t)k * n + i] = sx[i];
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) {
+            if (!conv[kk]) failed = true;
+            worst = max(worst, sweeps[kk]);
+        }
+        for (int kk = 0; kk < kn; ++kk)
+            for (int i = tid; i < n; i += TPB) X[(size_t)(k0 + kk) * n + i] = sx[kk][i];
         __syncthreads();
     }
     if (tid == 0) {

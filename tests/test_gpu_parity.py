@@ -162,6 +162,26 @@ def test_uneven_batch_matches_oracle(precision):
     assert e["cl"] < tol and e["cp"] < tol, e
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("wave_limit", [None, 0])
+def test_max_angles_per_airfoil(precision, wave_limit):
+    # K = 16 right-hand sides (the largest allowed) ride through the
+    # factorisation as extra columns: the widest trailing blocks, including
+    # n1 + K = 335 for the largest even panel count of the one-wavefront kernels.
+    _say(f"K = 16 angles, precision={precision}, wave_limit={wave_limit}")
+    w = synth.random_workload(17, 6, n_choices=(30, 64, 250, 300, 318), k_max=1)
+    rng = np.random.default_rng(17)
+    w = synth.Workload(w.name, w.m, w.p, w.t, np.array([30, 64, 250, 300, 316, 318], dtype=np.int32),
+                       [rng.uniform(-4.0, 12.0, 16) * DEG for _ in range(6)], True)
+    s, got = _run(w, precision, wave_limit=wave_limit)
+    ref = _oracle(w)
+    assert np.all(got["info"] == 0)
+    e = _errors(got, ref, w)
+    tol = TOL64 if precision == 0 else TOL32R
+    _say(f"  errors {e}")
+    assert e["cl"] < tol and e["cp"] < tol, e
+
+
 def test_closed_form_geometries_identical_inputs():
     # Cylinder and Joukowski nodes from the shared input generator, fed to both
     # sides.  Cusped Joukowski sections are much worse conditioned than the
