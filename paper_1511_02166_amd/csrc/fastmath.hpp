@@ -50,6 +50,14 @@ constexpr double kAtanQ1 = 0.24497866312686414;    // atan(1/4)
 constexpr double kAtanQ2 = 0.4636476090008061;     // atan(1/2)
 constexpr double kAtanQ3 = 0.6435011087932844;     // atan(3/4)
 constexpr double kAtanQ4 = 0.7853981633974483;     // atan(1) = pi/4
+// Series coefficients, read from constant memory: loaded once per kernel
+// into scalar registers, they enter each FMA as a scalar operand (written
+// as literals, the compiler keeps them in vector registers and copies one
+// into the accumulator of every Horner step).
+inline __constant__ double kLogPoly[10] = {2.0 / 21.0, 2.0 / 19.0, 2.0 / 17.0, 2.0 / 15.0, 2.0 / 13.0,
+                                           2.0 / 11.0, 2.0 / 9.0,  2.0 / 7.0,  2.0 / 5.0,  2.0 / 3.0};
+inline __constant__ double kAtanPoly[9] = {-1.0 / 19.0, 1.0 / 17.0, -1.0 / 15.0, 1.0 / 13.0, -1.0 / 11.0,
+                                           1.0 / 9.0,   -1.0 / 7.0, 1.0 / 5.0,   -1.0 / 3.0};
 }  // namespace fm
 
 __device__ __forceinline__ double plog(double x) {
@@ -61,16 +69,9 @@ __device__ __forceinline__ double plog(double x) {
     const double f = m - 1.0;
     const double s = pdiv(f, 2.0 + f);
     const double z = s * s;
-    double R = 2.0 / 21.0;
-    R = fma(R, z, 2.0 / 19.0);
-    R = fma(R, z, 2.0 / 17.0);
-    R = fma(R, z, 2.0 / 15.0);
-    R = fma(R, z, 2.0 / 13.0);
-    R = fma(R, z, 2.0 / 11.0);
-    R = fma(R, z, 2.0 / 9.0);
-    R = fma(R, z, 2.0 / 7.0);
-    R = fma(R, z, 2.0 / 5.0);
-    R = fma(R, z, 2.0 / 3.0);
+    double R = fm::kLogPoly[0];   // z (2/3 + 2z/5 + ... + 2z^9/21)
+#pragma unroll
+    for (int k = 1; k < 10; ++k) R = fma(R, z, fm::kLogPoly[k]);
     R *= z;
     const double lm = f - s * (f - R);
     const double ef = (double)e;
@@ -87,15 +88,9 @@ __device__ __forceinline__ double patan2(double y, double x) {
     const double c = 0.25 * fi;
     const double u = pdiv(fma(-c, den, num), fma(c, num, den));
     const double z = u * u;
-    double P = -1.0 / 19.0;
-    P = fma(P, z, 1.0 / 17.0);
-    P = fma(P, z, -1.0 / 15.0);
-    P = fma(P, z, 1.0 / 13.0);
-    P = fma(P, z, -1.0 / 11.0);
-    P = fma(P, z, 1.0 / 9.0);
-    P = fma(P, z, -1.0 / 7.0);
-    P = fma(P, z, 1.0 / 5.0);
-    P = fma(P, z, -1.0 / 3.0);
+    double P = fm::kAtanPoly[0];   // -1/3 + z/5 - ... - z^8/19
+#pragma unroll
+    for (int k = 1; k < 9; ++k) P = fma(P, z, fm::kAtanPoly[k]);
     const double at = fma(u * z, P, u);
     const int i = (int)fi;
     const double base = i == 0 ? 0.0 : i == 1 ? fm::kAtanQ1 : i == 2 ? fm::kAtanQ2 : i == 3 ? fm::kAtanQ3 : fm::kAtanQ4;
