@@ -618,7 +618,7 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
                     for (int j = 0; j < n; ++j) {
                         const double a = A[(size_t)j * ld + i];
                         s0 -= a * sx[0][j];
-                        s1 -= a * sx[1][j];
+                        if (kn > 1) s1 -= a * sx[1][j];
                         ra += fabs(a);
                     }
                 } else if (kn == 1) {

@@ -151,10 +151,13 @@ def test_fp32_refined_pipeline_matches_oracle(cfg, B, wave_limit):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_uneven_batch_matches_oracle(precision):
-    _say(f"uneven batch parity, precision={precision}")
+@pytest.mark.parametrize("wave_limit", [None, 0])
+def test_uneven_batch_matches_oracle(precision, wave_limit):
+    # K = 1..4 per airfoil: odd counts exercise the refinement's single
+    # right-hand-side tail in both kernel families
+    _say(f"uneven batch parity, precision={precision}, wave_limit={wave_limit}")
     w = synth.random_workload(11, 40, n_choices=(4, 6, 16, 30, 64, 96, 130, 250, 256, 300), k_max=4)
-    s, got = _run(w, precision)
+    s, got = _run(w, precision, wave_limit=wave_limit)
     ref = _oracle(w)
     assert np.all(got["info"] == 0)
     e = _errors(got, ref, w)
