@@ -47,7 +47,8 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, help="seeded workload (2 = GA-population batch)")
+    ap.add_argument("--workload", default="ga2048",
+                    help="seeded workload (synth.WORKLOADS; default: the GA-population batch)")
     ap.add_argument("--batch", type=int, default=None, help="truncate the batch (debugging only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=None,
@@ -82,7 +83,7 @@ def main():
         sys.exit(1)
     P.load_library()   # fails loudly without the HIP library
     dev = torch.device("cuda")
-    w = synth.workload(a.config, B=a.batch)
+    w = synth.workload(a.workload, B=a.batch)
     noff, aoff = w.node_offsets(), w.alpha_offsets()
     alpha = torch.as_tensor(w.alpha_flat(), device=dev)
     mpt = torch.as_tensor(w.mpt(), device=dev)
@@ -179,7 +180,7 @@ def main():
     dom = "lu_solve_f64" if lu_ms >= asm_ms else "assemble_f64"
     roof = dict(kern[dom])
     traffic = None
-    if dom == "lu_solve_f64" and a.config == 2 and a.batch is None and a.wave_limit is None:
+    if dom == "lu_solve_f64" and a.workload == "ga2048" and a.batch is None and a.wave_limit is None:
         import hashlib
         src = "lu_wave.hip"
         with open(os.path.join(os.path.dirname(P.__file__), "csrc", src), "rb") as f:

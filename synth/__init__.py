@@ -70,49 +70,47 @@ def _naca_draws(rng, B):
     return m, p, t
 
 
-def workload(cfg: int, B: int | None = None) -> Workload:
-    """The five seeded workloads (config k is seeded with k).
+# The seeded workloads: name -> (seed, airfoils).  Draws per workload, in a
+# fixed order: camber, camber position, thickness, then the angles, then the
+# panel counts.
+WORKLOADS = {
+    "naca128": (1, 32),        # 32 airfoils, N = 128, alpha = 4 deg
+    "ga2048": (2, 2048),       # GA population: 2048 airfoils, N = 256, alpha ~ U[-4, 12] deg
+    "uneven4096": (3, 4096),   # 4096 airfoils, N = 16 U{6..32}, alpha in {0, 4, 8, 12} deg
+    "adjoint1024": (4, 1024),  # 1024 airfoils, N = 256, alpha = 6 deg
+    "large256": (5, 256),      # 256 airfoils, N = 1024, alpha = -2, 0, ..., 12 deg
+}
 
-    1: 32 airfoils, N=128, alpha = 4 deg.
-    2: 2048 airfoils, N=256, alpha ~ U[-4, 12] deg (GA-population batch).
-    3: 4096 airfoils, N ~ 16*U{6..32}, alpha in {0, 4, 8, 12} deg.
-    4: 1024 airfoils, N=256, alpha = 6 deg (adjoint).
-    5: 256 airfoils, N=1024, 8 angles -2, 0, ..., 12 deg.
-    ``B`` truncates the batch to its first B airfoils (same draws).
-    """
-    rng = np.random.default_rng(cfg)
-    if cfg == 1:
-        full = 32
-        m, p, t = _naca_draws(rng, full)
+
+def workload(name: str, B: int | None = None) -> Workload:
+    """One of the seeded workloads in WORKLOADS (NACA 4-digit sections,
+    cosine spacing, closed trailing edge).  ``B`` truncates the batch to its
+    first B airfoils (same draws)."""
+    if name not in WORKLOADS:
+        raise ValueError(f"unknown workload {name!r} (known: {', '.join(WORKLOADS)})")
+    seed, full = WORKLOADS[name]
+    rng = np.random.default_rng(seed)
+    m, p, t = _naca_draws(rng, full)
+    if name == "naca128":
         n = np.full(full, 128, np.int32)
         alpha = [np.array([4.0 * DEG]) for _ in range(full)]
-    elif cfg == 2:
-        full = 2048
-        m, p, t = _naca_draws(rng, full)
+    elif name == "ga2048":
         a = rng.uniform(-4.0, 12.0, full) * DEG
         n = np.full(full, 256, np.int32)
         alpha = [np.array([x]) for x in a]
-    elif cfg == 3:
-        full = 4096
-        m, p, t = _naca_draws(rng, full)
+    elif name == "uneven4096":
         n = (16 * rng.integers(6, 33, full)).astype(np.int32)
         alpha = [np.array([0.0, 4.0, 8.0, 12.0]) * DEG for _ in range(full)]
-    elif cfg == 4:
-        full = 1024
-        m, p, t = _naca_draws(rng, full)
+    elif name == "adjoint1024":
         n = np.full(full, 256, np.int32)
         alpha = [np.array([6.0 * DEG]) for _ in range(full)]
-    elif cfg == 5:
-        full = 256
-        m, p, t = _naca_draws(rng, full)
+    else:   # large256
         n = np.full(full, 1024, np.int32)
         alpha = [np.arange(-2.0, 12.01, 2.0) * DEG for _ in range(full)]
-    else:
-        raise ValueError(f"unknown workload {cfg}")
-    w = Workload(f"cfg{cfg}", m, p, t, n, alpha, True, {"cfg": cfg})
+    w = Workload(name, m, p, t, n, alpha, True, {"seed": seed})
     if B is not None and B < full:
         w = w.subset(np.arange(B))
-        w.name = f"cfg{cfg}[:{B}]"
+        w.name = f"{name}[:{B}]"
     return w
 
 

@@ -70,12 +70,12 @@ def test_adjoint_matches_oracle_identical_nodes(prec, tol, wave_limit):
     assert e < tol
 
 
-def test_adjoint_naca_cfg4_sample():
-    # config-4 shape: N = 256, alpha = 6 deg; each side builds its own NACA nodes.
+def test_adjoint_naca_sample():
+    # N = 256, alpha = 6 deg; each side builds its own NACA nodes.
     import torch
     import paper_1511_02166_amd as P
-    _say("adjoint vs oracle, cfg4[:6] NACA N=256")
-    w = synth.workload(4, B=6)
+    _say("adjoint vs oracle, adjoint1024[:6] NACA N=256")
+    w = synth.workload("adjoint1024", B=6)
     s = _solver(w.node_offsets(), w.alpha_offsets())
     xy = s.naca4(torch.as_tensor(w.mpt(), device="cuda"))
     al = torch.as_tensor(w.alpha_flat(), device="cuda")
@@ -94,7 +94,7 @@ def test_adjoint_directional_central_differences():
     # the subtended angle has a kink and central differences are meaningless.
     import torch
     _say("adjoint vs central differences of the GPU forward (NACA, N=128)")
-    w = synth.workload(1, B=3)
+    w = synth.workload("naca128", B=3)
     s = _solver(w.node_offsets(), w.alpha_offsets())
     xy0 = s.naca4(torch.as_tensor(w.mpt(), device="cuda"))
     al = torch.as_tensor(w.alpha_flat(), device="cuda")
@@ -126,7 +126,7 @@ def test_naca_parameter_gradient_central_differences():
     import torch
     import paper_1511_02166_amd as P
     _say("dCl/d(m,p,t) vs central differences, h = 1e-6")
-    w = synth.workload(4, B=4)
+    w = synth.workload("adjoint1024", B=4)
     s = _solver(w.node_offsets(), w.alpha_offsets())
     mpt0 = torch.as_tensor(w.mpt(), device="cuda", dtype=torch.float64)
     al = torch.as_tensor(w.alpha_flat(), device="cuda")
@@ -165,7 +165,7 @@ def test_naca_parameter_gradient_matches_oracle():
     import torch
     import paper_1511_02166_amd as P
     _say("dCl/d(m,p,t) through the NACA vjp")
-    w = synth.workload(4, B=4)
+    w = synth.workload("adjoint1024", B=4)
     s = _solver(w.node_offsets(), w.alpha_offsets())
     mpt = torch.as_tensor(w.mpt(), device="cuda", dtype=torch.float64).requires_grad_(True)
     al = torch.as_tensor(w.alpha_flat(), device="cuda")

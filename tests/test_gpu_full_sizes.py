@@ -101,7 +101,7 @@ def _check_sample(w, got, idx, precision):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_ga_batch_2048_n256(precision):
-    w = synth.workload(2)
+    w = synth.workload("ga2048")
     _say(f"full GA batch: {w.B} x N=256, precision={precision}")
     s, _, got = _run_full(w, precision)
     _check_batch_properties(w, got, precision)
@@ -114,7 +114,7 @@ def test_ga_batch_2048_n256(precision):
 
 @pytest.mark.parametrize("precision", [1, 0])
 def test_uneven_batch_4096(precision):
-    w = synth.workload(3)
+    w = synth.workload("uneven4096")
     _say(f"uneven batch: {w.B} airfoils, N in [{w.n_panels.min()}, {w.n_panels.max()}], K=4, "
          f"precision={precision}")
     s, _, got = _run_full(w, precision)
@@ -124,7 +124,7 @@ def test_uneven_batch_4096(precision):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_large_sections_256_n1024(precision):
-    w = synth.workload(5)
+    w = synth.workload("large256")
     _say(f"large sections: {w.B} x N=1024, K=8, precision={precision}")
     s, _, got = _run_full(w, precision)
     _check_batch_properties(w, got, precision)
@@ -135,18 +135,18 @@ def test_large_sections_256_n1024(precision):
         assert it.max() <= 8
 
 
-@pytest.mark.parametrize("cfg,sample", [(4, 3), (5, 1)])
-def test_adjoint_full_batch(cfg, sample):
+@pytest.mark.parametrize("name,sample", [("adjoint1024", 3), ("large256", 1)])
+def test_adjoint_full_batch(name, sample):
     # Every airfoil: translation (the nodal gradients sum to zero) and scaling
     # (sum_k P_k . dCl/dP_k = Cl with the chord held fixed) invariants of the
     # discrete lift, with the seeds dcl applied.  Sampled airfoils: the
     # oracle's tangent-linear gradient, one sweep per angle.
     from concurrent.futures import ThreadPoolExecutor
     import torch
-    w = synth.workload(cfg)
-    _say(f"adjoint, full batch cfg shape: {w.B} x N={int(w.n_panels.max())}, K={len(w.alpha[0])}")
+    w = synth.workload(name)
+    _say(f"adjoint, full batch {name}: {w.B} x N={int(w.n_panels.max())}, K={len(w.alpha[0])}")
     s, xy, got = _run_full(w, 0)
-    rng = np.random.default_rng(cfg)
+    rng = np.random.default_rng(w.meta["seed"])
     dcl = rng.standard_normal(int(w.alpha_offsets()[-1]))
     g = s.adjoint(xy, torch.as_tensor(dcl, device="cuda")).cpu().numpy()
     torch.cuda.synchronize()

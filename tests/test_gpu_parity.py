@@ -80,8 +80,8 @@ def _run(w, precision, xy_flat=None, refine_tol=1e-10, max_iter=10, wave_limit=N
 
 
 def test_naca4_matches_oracle():
-    _say("naca4 parity: cfg3[:64] uneven N")
-    w = synth.workload(3, B=64)
+    _say("naca4 parity: uneven4096[:64]")
+    w = synth.workload("uneven4096", B=64)
     xy, _ = _gpu_inputs(w)
     ref, _ = oracle.workload_nodes(w)
     got = xy.cpu().numpy()
@@ -122,11 +122,11 @@ def test_assembly_entries_match_oracle():
             assert np.max(np.abs(rhs - Rr)) < 1e-15
 
 
-@pytest.mark.parametrize("cfg,B,wave_limit", [(1, 32, None), (2, 96, None), (2, 40, 0)])
-def test_fp64_pipeline_matches_oracle(cfg, B, wave_limit):
+@pytest.mark.parametrize("name,B,wave_limit", [("naca128", 32, None), ("ga2048", 96, None), ("ga2048", 40, 0)])
+def test_fp64_pipeline_matches_oracle(name, B, wave_limit):
     import paper_1511_02166_amd as P
-    _say(f"fp64 pipeline parity: cfg{cfg}[:{B}], wave_limit={wave_limit}")
-    w = synth.workload(cfg, B=B)
+    _say(f"fp64 pipeline parity: {name}[:{B}], wave_limit={wave_limit}")
+    w = synth.workload(name, B=B)
     s, got = _run(w, P.PANEL_FP64, wave_limit=wave_limit)
     ref = _oracle(w)
     assert np.all(got["info"] == 0) and np.all(ref["info"] == 0)
@@ -135,11 +135,11 @@ def test_fp64_pipeline_matches_oracle(cfg, B, wave_limit):
     assert e["cl"] < TOL64 and e["cp"] < TOL64 and e["cl_p"] < TOL64, e
 
 
-@pytest.mark.parametrize("cfg,B,wave_limit", [(1, 32, None), (2, 96, None), (2, 40, 0)])
-def test_fp32_refined_pipeline_matches_oracle(cfg, B, wave_limit):
+@pytest.mark.parametrize("name,B,wave_limit", [("naca128", 32, None), ("ga2048", 96, None), ("ga2048", 40, 0)])
+def test_fp32_refined_pipeline_matches_oracle(name, B, wave_limit):
     import paper_1511_02166_amd as P
-    _say(f"fp32+refine pipeline parity: cfg{cfg}[:{B}], wave_limit={wave_limit}")
-    w = synth.workload(cfg, B=B)
+    _say(f"fp32+refine pipeline parity: {name}[:{B}], wave_limit={wave_limit}")
+    w = synth.workload(name, B=B)
     s, got = _run(w, P.PANEL_FP32_REFINE, wave_limit=wave_limit)
     ref = _oracle(w)
     assert np.all(got["info"] == 0)
@@ -253,7 +253,7 @@ def test_info_codes_for_bad_geometry():
 def test_refinement_budget_exhausted_reports_minus_two():
     import paper_1511_02166_amd as P
     _say("refinement with max_iter=0 / unreachable tolerance")
-    w = synth.workload(2, B=4)
+    w = synth.workload("ga2048", B=4)
     _, got = _run(w, P.PANEL_FP32_REFINE, max_iter=0)
     assert np.all(got["info"] == -2)
     # one sweep cannot verify convergence: the FP32 start is far from the
@@ -267,7 +267,7 @@ def test_graph_replay_matches_eager():
     import paper_1511_02166_amd as P
     torch = _torch()
     _say("hip graph capture/replay")
-    w = synth.workload(2, B=64)
+    w = synth.workload("ga2048", B=64)
     xy, alpha = _gpu_inputs(w)
     for prec in (P.PANEL_FP64, P.PANEL_FP32_REFINE):
         s = P.PanelSolver(w.node_offsets(), w.alpha_offsets(), prec)
