@@ -32,6 +32,7 @@ class PanelSolver:
         self.plan = B.Plan(node_offsets, alpha_offsets, precision)
         if wave_limit is not None:
             B.panel_plan_set_wave_limit(self.plan, wave_limit)
+        self.wave_limit = 320 if wave_limit is None else int(wave_limit)
         self.precision = int(precision)
         p = self.plan
         self._ws_raw, self.ws = _aligned_workspace(p.workspace_size(), self.device)
@@ -47,6 +48,36 @@ class PanelSolver:
     @property
     def B(self) -> int:
         return self.plan.B
+
+    def set_wave_limit(self, max_n1: int):
+        """Systems of order <= max_n1 go to the one-wavefront kernels (0..320)."""
+        B.panel_plan_set_wave_limit(self.plan, max_n1)
+        B.panel_workspace_init(self.plan, self.ws)
+        self.wave_limit = int(max_n1)
+
+    def autotune(self, xy, alpha, chord=None, vinf=1.0, refine_tol=1e-10, max_iter=10, candidates=(320, 0),
+                 reps=3):
+        """Measure the step (assembly -> factor/solve -> forces) on this batch
+        for each kernel choice and keep the fastest.
+
+        The one-wavefront kernels win when there are more systems than SIMDs;
+        with few systems (or for the refinement of small batches) a
+        workgroup per system uses the chip better.  Returns {limit: ms}."""
+        times = {}
+        for lim in candidates:
+            self.set_wave_limit(lim)
+            self.step(xy, alpha, chord, vinf, refine_tol, max_iter)
+            torch.cuda.synchronize(self.device)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                self.step(xy, alpha, chord, vinf, refine_tol, max_iter)
+            e1.record()
+            torch.cuda.synchronize(self.device)
+            times[lim] = e0.elapsed_time(e1) / reps
+        self.set_wave_limit(min(times, key=times.get))
+        return times
 
     # -- steps ---------------------------------------------------------------
     def naca4(self, mpt: torch.Tensor, closed_te: bool = True, out: torch.Tensor | None = None):

@@ -340,3 +340,23 @@ def test_lu_factors_reproduce_matrix(precision, sizes, wave_limit):
         assert res < tol * n, (N, res)
         ry = np.max(np.abs(Lm @ Y.T.astype(np.float64) - PR.T)) / np.max(np.abs(R))
         assert ry < tol * n, (N, ry)
+
+
+def test_autotune_picks_a_kernel_and_keeps_results():
+    # the measured kernel choice changes which kernels run, not the answer
+    import paper_1511_02166_amd as P
+    torch = _torch()
+    w = synth.workload("ga2048", B=128)
+    _say("autotune of the kernel choice, 128 airfoils, both precisions")
+    ref = _oracle(w)
+    for prec, tol in ((P.PANEL_FP64, TOL64), (P.PANEL_FP32_REFINE, TOL32R)):
+        xy, alpha = _gpu_inputs(w)
+        s = P.PanelSolver(w.node_offsets(), w.alpha_offsets(), prec)
+        times = s.autotune(xy, alpha)
+        _say(f"  precision {prec}: {times} -> wave limit {s.wave_limit}")
+        assert set(times) == {320, 0} and s.wave_limit == min(times, key=times.get)
+        out = s.solve(xy, alpha)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        e = _errors(got, ref, w)
+        assert np.all(got["info"] == 0) and e["cl"] < tol and e["cp"] < tol, e
