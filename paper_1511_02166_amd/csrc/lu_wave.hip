@@ -80,6 +80,20 @@ __device__ inline f4w_t mfma_t(float a, float b, f4w_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Hide a value from loop-invariant code motion.  Without this the compiler
+// forms address offsets (from ld) and lane-dependent constants once at the
+// start of the kernel and keeps them live across every phase, which pushes
+// the FP64 kernel past its 256 registers and spills them to scratch memory;
+// behind the barrier they are formed where they are used.
+__device__ __forceinline__ int opaque_s(int v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+__device__ __forceinline__ int opaque_v(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 template <typename T> __device__ inline T *sys_of(const WsView &v, const AirfoilMeta &mt);
 template <> __device__ inline double *sys_of<double>(const WsView &v, const AirfoilMeta &mt) {
     return v.a64 + mt.a_off;
@@ -123,6 +137,7 @@ template <typename T> struct WaveLds {
 template <typename T, int NBLK, int NT>
 __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int kend, int cs, int c1,
                                              const WaveLds<T> &S, int slot0, int nblk) {
+    ld = opaque_s(ld);
     constexpr int S4 = 4 * NBLK;   // k-steps (4 rows each) of the band
     typedef typename TileMap<T>::acc acc_t;
     const int lane = threadIdx.x, i16 = lane & 15, k4 = lane >> 4;
@@ -385,6 +400,7 @@ __device__ __forceinline__ void wave_cols(T (&p)[R][WNB], int (&pos)[R], unsigne
 // ---- factor the panel of columns k0..k0+nb-1 (rows k0..n-1, R = rows/64) --
 template <typename T, int R>
 __device__ __forceinline__ void wave_panel(T *A, int ld, int n, int k0, int nb, int32_t *piv, int &info, WaveLds<T> &S) {
+    ld = opaque_s(ld);
     const int lane = threadIdx.x;
     T p[R][WNB];
     int pos[R];
@@ -448,6 +464,7 @@ template <typename T>
 __device__ __forceinline__ void wave_moves(T *A, int ld, int ncols, int k0, int nb, const WaveLds<T> &S) {
     const int nmv = __builtin_amdgcn_readfirstlane(S.nmv);
     if (nmv == 0) return;
+    ld = opaque_s(ld);
     const int lane = threadIdx.x;
 #pragma unroll 1
     for (int j = lane; j < ncols; j += WL) {
@@ -468,7 +485,7 @@ __device__ __forceinline__ void wave_moves(T *A, int ld, int ncols, int k0, int 
 // Lane j < 16 solves L x = e_j by forward substitution (L from LDS).
 template <typename T>
 __device__ __forceinline__ void wave_linv(WaveLds<T> &S, int slot) {
-    const int lane = threadIdx.x;
+    const int lane = opaque_v(threadIdx.x);
     if (lane < WNB) {
         T x[WNB];
 #pragma unroll
@@ -494,6 +511,7 @@ __device__ __forceinline__ void wave_linv(WaveLds<T> &S, int slot) {
 // above take the block's contribution.
 template <typename T, bool BATCH>
 __device__ __forceinline__ void wave_trsv_upper(const T *U, int ld, int n, T *y) {
+    ld = opaque_s(ld);
     const int lane = threadIdx.x;
     for (int rb = ((n - 1) / WL) * WL; rb >= 0; rb -= WL) {
         const int w = min(WL, n - rb);
