@@ -65,6 +65,14 @@ template <> __device__ inline float *sys_base<float>(const WsView &v, const Airf
     return v.a32 + mt.a_off;
 }
 
+// Hide a value from loop-invariant code motion, so that address offsets
+// derived from it are formed where they are used instead of being hoisted
+// to the start of the kernel and kept (or spilled) across every phase.
+__device__ __forceinline__ int opaque_s(int v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
 // Pivot candidate order: larger magnitude wins, lower row index on ties.
 __device__ inline bool better(double va, int ia, double vb, int ib) {
     return va > vb || (va == vb && ia < ib);
@@ -157,8 +165,11 @@ __device__ void trsv_lower_unit(const T *L, int ld, int n, V *y, T *sblk) {
 }
 
 // LDS scratch of one workgroup's panel factorisation.
-template <typename T, int NB> struct PanelLds {
-    T crow[2][TPB / 64][NB];   // each wavefront's pivot candidate row (double-buffered)
+template <typename T, int NB, int R> struct PanelLds {
+    // each wavefront's pivot candidate: all R rows of the thread that holds
+    // it (double-buffered); cq names the one that is the candidate
+    T crow[2][TPB / 64][R][NB];
+    int cq[2][TPB / 64];
     T grow[2][NB];             // row g (the one the pivot replaces)
     double cval[2][TPB / 64];  // candidate |a|
     int cidx[2][TPB / 64];     // candidate row index
@@ -172,9 +183,8 @@ template <typename T, int NB> struct PanelLds {
 // candidate row, and the owner of row g publishes row g, so after the
 // barrier each thread can perform the exchange and the rank-1 update on its
 // own rows.  The LDS slots are double-buffered by column parity.
-template <typename T, int NB, int R, int C>
-__device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int n, int &info,
-                                           PanelLds<T, NB> &L) {
+template <typename T, int NB, int R, int C, typename Lds>
+__device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int n, int &info, Lds &L) {
     constexpr int buf = C & 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = k0 + C;
@@ -206,14 +216,16 @@ __device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int n, int &in
     }
     if (!(wbest >= 0.0)) widx = INT_MAX;   // no row of this wavefront is eligible
     if (lane == wlane) {
+        // all of the thread's rows go out: picking row bq here would index
+        // the register array with a run-time value, which puts the whole
+        // panel in scratch memory
         L.cval[buf][wave] = wbest;
         L.cidx[buf][wave] = widx;
+        L.cq[buf][wave] = bq;
 #pragma unroll
         for (int q = 0; q < R; ++q)
-            if (q == bq) {
 #pragma unroll
-                for (int cc = 0; cc < NB; ++cc) L.crow[buf][wave][cc] = p[q][cc];
-            }
+            for (int cc = 0; cc < NB; ++cc) L.crow[buf][wave][q][cc] = p[q][cc];
     }
     if (tid == C) {
 #pragma unroll
@@ -240,16 +252,17 @@ __device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int n, int &in
         if (info == 0) info = g + 1;
         return;
     }
-    const T *u = L.crow[buf][pw];
+    const T *u = L.crow[buf][pw][L.cq[buf][pw]];
     if (pr != g) {
         const int pown = (pr - k0) & (TPB - 1), pq = (pr - k0) / TPB;
         if (tid == pown) {
+            // (a select per slot, for the same reason as above)
 #pragma unroll
-            for (int q = 0; q < R; ++q)
-                if (q == pq) {
+            for (int cc = 0; cc < NB; ++cc) {
+                const T t = L.grow[buf][cc];
 #pragma unroll
-                    for (int cc = 0; cc < NB; ++cc) p[q][cc] = L.grow[buf][cc];
-                }
+                for (int q = 0; q < R; ++q) p[q][cc] = (q == pq) ? t : p[q][cc];
+            }
         }
         if (tid == C) {
 #pragma unroll
@@ -269,15 +282,65 @@ __device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int n, int &in
     }
 }
 
-template <typename T, int NB, int R, int C>
-__device__ __forceinline__ void panel_steps(T (&p)[R][NB], int k0, int nb, int n, int &info,
-                                            PanelLds<T, NB> &L) {
+template <typename T, int NB, int R, int C, typename Lds>
+__device__ __forceinline__ void panel_steps(T (&p)[R][NB], int k0, int nb, int n, int &info, Lds &L) {
     if constexpr (C < NB) {
         if (C < nb) {
             panel_step<T, NB, R, C>(p, k0, n, info, L);
             panel_steps<T, NB, R, C + 1>(p, k0, nb, n, info, L);
         }
     }
+}
+
+// Steps 1-3 of one pivot panel (columns k0..k0+nb-1, rows k0..n-1, R =
+// rows / TPB rounded up): rows into registers, factorisation, rows back to
+// memory, L11 to LDS, pivots out.  R is chosen per panel, so the later
+// panels of a system (fewer rows) run the smaller instances.
+template <typename T, int NB, int R, typename Lds>
+__device__ __forceinline__ void wg_panel(T *A, int ld, int n, int k0, int nb, int32_t *piv, int &info, Lds &L,
+                                         T (*s_L11)[NB + 1]) {
+    ld = opaque_s(ld);
+    const int tid = threadIdx.x;
+    T p[R][NB];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = k0 + tid + TPB * q;
+        const int rr = r < n ? r : n - 1;
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) {
+            const T t = A[(size_t)min(k0 + cc, n - 1) * ld + rr];
+            p[q][cc] = (r < n && cc < nb) ? t : T(0);
+        }
+    }
+    panel_steps<T, NB, R, 0>(p, k0, nb, n, info, L);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = k0 + tid + TPB * q;
+        if (r < n) {
+            if (nb == NB) {
+#pragma unroll
+                for (int cc = 0; cc < NB; ++cc) A[(size_t)(k0 + cc) * ld + r] = p[q][cc];
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < NB; ++cc)
+                    if (cc < nb) A[(size_t)(k0 + cc) * ld + r] = p[q][cc];
+            }
+        }
+    }
+    if (tid < NB) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) s_L11[tid][cc] = (tid < nb) ? p[0][cc] : T(0);
+        if (tid < nb) piv[k0 + tid] = L.piv[tid];
+    }
+}
+
+template <typename T, int NB, int R, typename Lds>
+__device__ __forceinline__ bool wg_panel_if(int rows, T *A, int ld, int n, int k0, int nb, int32_t *piv, int &info,
+                                            Lds &L, T (*s_L11)[NB + 1]) {
+    if (rows != R) return false;
+    wg_panel<T, NB, R>(A, ld, n, k0, nb, piv, info, L, s_L11);
+    return true;
 }
 
 // U12 = L11^{-1} A12 for columns [cs, cs + cw) (cw <= CH), rows k0..k0+nb:
@@ -287,6 +350,7 @@ __device__ __forceinline__ void panel_steps(T (&p)[R][NB], int k0, int nb, int n
 template <typename T, int NB>
 __device__ __forceinline__ void trsm_cols(T *A, int ld, int k0, int nb, int cs, int cw,
                                           const T (*sL)[NB + 1], T *Us) {
+    ld = opaque_s(ld);
     const int tid = threadIdx.x;
     T u[NB];
     // rows k0..k0+NB-1 always lie inside the column (ld is a multiple of NB);
@@ -325,6 +389,7 @@ __device__ __forceinline__ void trsm_cols(T *A, int ld, int k0, int nb, int cs, 
 template <typename T, int KD, bool BK>
 __device__ __forceinline__ void gemm_sub(T *A, int ld, int rowA, int rowEnd, int colA, int ncol, int kb,
                                          const T *Bs, int ldb, int bcol0) {
+    ld = opaque_s(ld);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, k4 = lane >> 4;
     const int nrt = (rowEnd - rowA + 15) >> 4;
@@ -369,8 +434,11 @@ __device__ __forceinline__ void gemm_sub(T *A, int ld, int rowA, int rowEnd, int
     }
 }
 
-template <typename T, int NB, int R>
-__global__ __launch_bounds__(TPB, 2) void lu_kernel(WsView v, int32_t *__restrict__ info_out) {
+// RMAX: largest number of rows per thread in a panel (n1 <= TPB * RMAX).
+// Up to three rows per thread two workgroups share a CU; the instance for
+// the largest systems (up to five) takes the whole register file of one.
+template <typename T, int NB, int RMAX>
+__global__ __launch_bounds__(TPB, RMAX <= 3 ? 2 : 1) void lu_kernel(WsView v, int32_t *__restrict__ info_out) {
     const int b = v.order[blockIdx.x];
     const AirfoilMeta mt = v.meta[b];
     const int n = mt.n1, ld = mt.ld, ncols = mt.n1 + mt.K;
@@ -386,12 +454,10 @@ __global__ __launch_bounds__(TPB, 2) void lu_kernel(WsView v, int32_t *__restric
     T *A = sys_base<T>(v, mt);
     int32_t *piv = v.piv + mt.piv_off;
 
-    __shared__ PanelLds<T, NB> L;
+    __shared__ PanelLds<T, NB, RMAX> L;
     __shared__ T s_L11[NB][NB + 1];
     __shared__ T s_U[NB][CH + 4];   // also holds the CT x (SP + 1) band of step 6
     int info = 0;
-
-    T p[R][NB];
 
     // Super-panels of SP columns; inside, NB-column pivot panels update the
     // super-panel's own columns fully but only the super-panel's rows of the
@@ -401,42 +467,13 @@ __global__ __launch_bounds__(TPB, 2) void lu_kernel(WsView v, int32_t *__restric
     for (int k0 = K0; k0 < kend; k0 += NB) {
         const int nb = min(NB, n - k0);
 
-        // ---- 1. panel rows k0..n-1 into registers ------------------------
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int r = k0 + tid + TPB * q;
-            const int rr = r < n ? r : n - 1;
-#pragma unroll
-            for (int cc = 0; cc < NB; ++cc) {
-                const T t = A[(size_t)min(k0 + cc, n - 1) * ld + rr];
-                p[q][cc] = (r < n && cc < nb) ? t : T(0);
-            }
-        }
-
-        // ---- 2. factorise the panel ---------------------------------------
-        panel_steps<T, NB, R, 0>(p, k0, nb, n, info, L);
-        __syncthreads();
-
-        // ---- 3. panel back to memory, L11 to LDS, pivots out -------------
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int r = k0 + tid + TPB * q;
-            if (r < n) {
-                if (nb == NB) {
-#pragma unroll
-                    for (int cc = 0; cc < NB; ++cc) A[(size_t)(k0 + cc) * ld + r] = p[q][cc];
-                } else {
-#pragma unroll
-                    for (int cc = 0; cc < NB; ++cc)
-                        if (cc < nb) A[(size_t)(k0 + cc) * ld + r] = p[q][cc];
-                }
-            }
-        }
-        if (tid < NB) {
-#pragma unroll
-            for (int cc = 0; cc < NB; ++cc) s_L11[tid][cc] = (tid < nb) ? p[0][cc] : T(0);
-            if (tid < nb) piv[k0 + tid] = L.piv[tid];
-        }
+        // ---- 1.-3. the panel: load, factorise, store ------------------------
+        const int rows = (n - k0 + TPB - 1) / TPB;
+        wg_panel_if<T, NB, 1>(rows, A, ld, n, k0, nb, piv, info, L, s_L11) ||
+            wg_panel_if<T, NB, (RMAX >= 2 ? 2 : 1)>(rows, A, ld, n, k0, nb, piv, info, L, s_L11) ||
+            wg_panel_if<T, NB, (RMAX >= 3 ? 3 : 1)>(rows, A, ld, n, k0, nb, piv, info, L, s_L11) ||
+            wg_panel_if<T, NB, (RMAX >= 4 ? 4 : 1)>(rows, A, ld, n, k0, nb, piv, info, L, s_L11) ||
+            wg_panel_if<T, NB, (RMAX >= 5 ? 5 : 1)>(rows, A, ld, n, k0, nb, piv, info, L, s_L11);
         __syncthreads();
 
         // ---- 4. the panel's row exchanges on every other column ------------
@@ -686,22 +723,13 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
     }
 }
 
-template <typename T, int NB, int R>
-void launch_lu(const WsView &v, int32_t B, int32_t *info, hipStream_t s) {
-    lu_kernel<T, NB, R><<<B, TPB, 0, s>>>(v, info);
-}
-
 template <typename T>
 hipError_t launch_lu_any(const WsView &v, int32_t B, int32_t max_n1, int32_t *info, hipStream_t s) {
     const int R = (max_n1 + TPB - 1) / TPB;
-    if (R <= 1)
-        launch_lu<T, 16, 1>(v, B, info, s);
-    else if (R == 2)
-        launch_lu<T, 16, 2>(v, B, info, s);
-    else if (R == 3)
-        launch_lu<T, 16, 3>(v, B, info, s);
+    if (R <= 3)
+        lu_kernel<T, 16, 3><<<B, TPB, 0, s>>>(v, info);
     else
-        launch_lu<T, 16, 5>(v, B, info, s);
+        lu_kernel<T, 16, 5><<<B, TPB, 0, s>>>(v, info);
     return hipGetLastError();
 }
 
