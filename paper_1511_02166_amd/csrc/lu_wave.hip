@@ -22,8 +22,10 @@
 //     LAPACK's explicit row exchanges produce;
 //   * the same row moves are applied to every other column as one gather /
 //     scatter per column;
-//   * the panel updates the super-panel's remaining columns at once
-//     (triangular solve on its rows, rank-16 update below);
+//   * inside the super-panel the update is left-looking: before a panel is
+//     factored, its 16 columns take the triangular solves and the rank-16p
+//     update from the p panels before it in one pass (each column block is
+//     read and written once, instead of once per earlier panel);
 //   * columns right of the super-panel only receive the row moves until the
 //     super-panel is complete; then its four triangular solves and in-band
 //     updates turn their top rows into U12, and one rank-64 update
@@ -212,10 +214,10 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
             coff[t][e] = min(c, c1 - 1) * ld;
         }
     const T *lcol = A + (size_t)(kb + k4) * ld;
-    if constexpr (NBLK == 1) {
-        // little work per tile (8 products): D tiles in flight; each step
-        // computes one tile and issues the loads of the tile D - 1 ahead
-        // into the slot just freed
+    if constexpr (NBLK == 1 || (NT == 1 && NBLK <= 3)) {
+        // little work per tile (at most 12 dependent products): D tiles in
+        // flight; each step computes one tile and issues the loads of the
+        // tile D - 1 ahead into the slot just freed
         constexpr int D = 4;
         T lf[D][S4];
         acc_t acc[D][NT];
@@ -594,6 +596,13 @@ __global__ __launch_bounds__(WL, 2) void lu_wave_kernel(WsView v, int32_t first,
         for (int k0 = K0; k0 < kend; k0 += WNB) {
             const int nb = min(WNB, n - k0);
             const int rows = (n - k0 + WL - 1) / WL;
+            // the panel's columns take the update from the super-panel's
+            // panels before it, all at once (left-looking inside the
+            // super-panel: each column block is read and written once)
+            if (k0 - K0 == WNB) wave_update<T, 1>(A, ld, n, K0, k0, k0, k0 + nb, S, 0);
+            if (k0 - K0 == 2 * WNB) wave_update<T, 2>(A, ld, n, K0, k0, k0, k0 + nb, S, 0);
+            if (k0 - K0 == 3 * WNB) wave_update<T, 3>(A, ld, n, K0, k0, k0, k0 + nb, S, 0);
+            if (k0 > K0) __syncthreads();
             panel_if<T, 1>(rows, A, ld, n, k0, nb, piv, info, S) ||
                 panel_if<T, 2>(rows, A, ld, n, k0, nb, piv, info, S) ||
                 panel_if<T, 3>(rows, A, ld, n, k0, nb, piv, info, S) ||
@@ -603,12 +612,6 @@ __global__ __launch_bounds__(WL, 2) void lu_wave_kernel(WsView v, int32_t first,
             wave_moves<T>(A, ld, ncols, k0, nb, S);
             wave_linv<T>(S, (k0 - K0) / WNB);
             __syncthreads();
-            // the panel's U rows and rank-16 update for the super-panel's
-            // remaining columns
-            if (k0 + nb < kend) {
-                wave_update<T, 1>(A, ld, n, k0, k0 + nb, k0 + nb, kend, S, (k0 - K0) / WNB);
-                __syncthreads();
-            }
         }
         // columns right of the super-panel: U12 rows and the rank-64 update
         if (kend < ncols) {
