@@ -86,13 +86,13 @@ __device__ inline bool better(double va, int ia, double vb, int ib) {
 // the whole workgroup.
 
 // Back substitution U x = y (U upper, column-major in global memory), y in LDS.
-template <typename T, typename V>
+template <typename T, typename V, int TB = TPB>
 __device__ void trsv_upper(const T *U, int ld, int n, V *y, T *sblk) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = (n + SB - 1) / SB;
     for (int blk = nblk - 1; blk >= 0; --blk) {
         const int rb = blk * SB, w = min(SB, n - rb);
-        for (int idx = tid; idx < SB * SB; idx += TPB) {
+        for (int idx = tid; idx < SB * SB; idx += TB) {
             const int c = idx >> 6, r = idx & 63;
             sblk[idx] = (c < w && r <= c) ? U[(size_t)(rb + c) * ld + rb + r] : T(0);
         }
@@ -108,7 +108,7 @@ __device__ void trsv_upper(const T *U, int ld, int n, V *y, T *sblk) {
             if (lane < w) y[rb + lane] = yi;
         }
         __syncthreads();
-        for (int r = tid; r < rb; r += TPB) {
+        for (int r = tid; r < rb; r += TB) {
             const T *up = U + (size_t)rb * ld + r;
             if (w == SB) {   // every block but the last, partial one
                 V s0 = y[r], s1 = V(0);
@@ -129,13 +129,13 @@ __device__ void trsv_upper(const T *U, int ld, int n, V *y, T *sblk) {
 }
 
 // Forward substitution L y = b (unit lower), y in LDS.
-template <typename T, typename V>
+template <typename T, typename V, int TB = TPB>
 __device__ void trsv_lower_unit(const T *L, int ld, int n, V *y, T *sblk) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = (n + SB - 1) / SB;
     for (int blk = 0; blk < nblk; ++blk) {
         const int rb = blk * SB, w = min(SB, n - rb);
-        for (int idx = tid; idx < SB * SB; idx += TPB) {
+        for (int idx = tid; idx < SB * SB; idx += TB) {
             const int c = idx >> 6, r = idx & 63;
             sblk[idx] = (c < w && r < w && r > c) ? L[(size_t)(rb + c) * ld + rb + r] : T(0);
         }
@@ -149,7 +149,7 @@ __device__ void trsv_lower_unit(const T *L, int ld, int n, V *y, T *sblk) {
             if (lane < w) y[rb + lane] = yi;
         }
         __syncthreads();
-        for (int r = rb + w + tid; r < n; r += TPB) {
+        for (int r = rb + w + tid; r < n; r += TB) {
             // rows below a block exist only when the block is full (w == SB)
             V s0 = y[r], s1 = V(0);
             const T *lp = L + (size_t)rb * ld + r;
@@ -165,25 +165,25 @@ __device__ void trsv_lower_unit(const T *L, int ld, int n, V *y, T *sblk) {
 }
 
 // LDS scratch of one workgroup's panel factorisation.
-template <typename T, int NB, int R> struct PanelLds {
+template <typename T, int NB, int R, int TB> struct PanelLds {
     // each wavefront's pivot candidate: all R rows of the thread that holds
     // it (double-buffered); cq names the one that is the candidate
-    T crow[2][TPB / 64][R][NB];
-    int cq[2][TPB / 64];
+    T crow[2][TB / 64][R][NB];
+    int cq[2][TB / 64];
     T grow[2][NB];             // row g (the one the pivot replaces)
-    double cval[2][TPB / 64];  // candidate |a|
-    int cidx[2][TPB / 64];     // candidate row index
+    double cval[2][TB / 64];  // candidate |a|
+    int cidx[2][TB / 64];     // candidate row index
     int piv[NB];               // pivot row chosen at each column of the panel
 };
 
 // One column step of the panel factorisation.  Rows are held one per thread
-// (row k0 + tid + TPB q in p[q][.]); C is a compile-time column index so the
+// (row k0 + tid + TB q in p[q][.]); C is a compile-time column index so the
 // register array is only indexed with constants.  One barrier per column:
 // every wavefront publishes its best candidate together with the whole
 // candidate row, and the owner of row g publishes row g, so after the
 // barrier each thread can perform the exchange and the rank-1 update on its
 // own rows.  The LDS slots are double-buffered by column parity.
-template <typename T, int NB, int R, int C, typename Lds>
+template <typename T, int NB, int R, int C, int TB, typename Lds>
 __device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int n, int &info, Lds &L) {
     constexpr int buf = C & 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -194,7 +194,7 @@ __device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int n, int &in
     int bidx = INT_MAX, bq = 0;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        const int r = k0 + tid + TPB * q;
+        const int r = k0 + tid + TB * q;
         const double a = fabs((double)p[q][C]);
         if (r >= g && r < n && a > best) {
             best = a;
@@ -235,7 +235,7 @@ __device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int n, int &in
     double pv = L.cval[buf][0];
     int pr = L.cidx[buf][0], pw = 0;
 #pragma unroll
-    for (int w = 1; w < TPB / 64; ++w) {
+    for (int w = 1; w < TB / 64; ++w) {
         const double v = L.cval[buf][w];
         const int i = L.cidx[buf][w];
         if (better(v, i, pv, pr)) {
@@ -254,7 +254,7 @@ __device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int n, int &in
     }
     const T *u = L.crow[buf][pw][L.cq[buf][pw]];
     if (pr != g) {
-        const int pown = (pr - k0) & (TPB - 1), pq = (pr - k0) / TPB;
+        const int pown = (pr - k0) & (TB - 1), pq = (pr - k0) / TB;
         if (tid == pown) {
             // (a select per slot, for the same reason as above)
 #pragma unroll
@@ -272,7 +272,7 @@ __device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int n, int &in
     const T piv = u[C];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        const int r = k0 + tid + TPB * q;
+        const int r = k0 + tid + TB * q;
         if (r > g && r < n) {
             const T l = p[q][C] / piv;
             p[q][C] = l;
@@ -282,21 +282,21 @@ __device__ __forceinline__ void panel_step(T (&p)[R][NB], int k0, int n, int &in
     }
 }
 
-template <typename T, int NB, int R, int C, typename Lds>
+template <typename T, int NB, int R, int C, int TB, typename Lds>
 __device__ __forceinline__ void panel_steps(T (&p)[R][NB], int k0, int nb, int n, int &info, Lds &L) {
     if constexpr (C < NB) {
         if (C < nb) {
-            panel_step<T, NB, R, C>(p, k0, n, info, L);
-            panel_steps<T, NB, R, C + 1>(p, k0, nb, n, info, L);
+            panel_step<T, NB, R, C, TB>(p, k0, n, info, L);
+            panel_steps<T, NB, R, C + 1, TB>(p, k0, nb, n, info, L);
         }
     }
 }
 
 // Steps 1-3 of one pivot panel (columns k0..k0+nb-1, rows k0..n-1, R =
-// rows / TPB rounded up): rows into registers, factorisation, rows back to
+// rows / TB rounded up): rows into registers, factorisation, rows back to
 // memory, L11 to LDS, pivots out.  R is chosen per panel, so the later
 // panels of a system (fewer rows) run the smaller instances.
-template <typename T, int NB, int R, typename Lds>
+template <typename T, int NB, int R, int TB, typename Lds>
 __device__ __forceinline__ void wg_panel(T *A, int ld, int n, int k0, int nb, int32_t *piv, int &info, Lds &L,
                                          T (*s_L11)[NB + 1]) {
     ld = opaque_s(ld);
@@ -304,7 +304,7 @@ __device__ __forceinline__ void wg_panel(T *A, int ld, int n, int k0, int nb, in
     T p[R][NB];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        const int r = k0 + tid + TPB * q;
+        const int r = k0 + tid + TB * q;
         const int rr = r < n ? r : n - 1;
 #pragma unroll
         for (int cc = 0; cc < NB; ++cc) {
@@ -312,11 +312,11 @@ __device__ __forceinline__ void wg_panel(T *A, int ld, int n, int k0, int nb, in
             p[q][cc] = (r < n && cc < nb) ? t : T(0);
         }
     }
-    panel_steps<T, NB, R, 0>(p, k0, nb, n, info, L);
+    panel_steps<T, NB, R, 0, TB>(p, k0, nb, n, info, L);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        const int r = k0 + tid + TPB * q;
+        const int r = k0 + tid + TB * q;
         if (r < n) {
             if (nb == NB) {
 #pragma unroll
@@ -335,11 +335,11 @@ __device__ __forceinline__ void wg_panel(T *A, int ld, int n, int k0, int nb, in
     }
 }
 
-template <typename T, int NB, int R, typename Lds>
+template <typename T, int NB, int R, int TB, typename Lds>
 __device__ __forceinline__ bool wg_panel_if(int rows, T *A, int ld, int n, int k0, int nb, int32_t *piv, int &info,
                                             Lds &L, T (*s_L11)[NB + 1]) {
     if (rows != R) return false;
-    wg_panel<T, NB, R>(A, ld, n, k0, nb, piv, info, L, s_L11);
+    wg_panel<T, NB, R, TB>(A, ld, n, k0, nb, piv, info, L, s_L11);
     return true;
 }
 
@@ -386,7 +386,7 @@ __device__ __forceinline__ void trsm_cols(T *A, int ld, int k0, int nb, int cs, 
 // when BK is true (k-major) and Bs[c * ldb + k] otherwise, c counted from
 // bcol0.  Each wavefront takes row tiles; it keeps the tile's A fragments in
 // registers and streams four 16x16 C tiles at a time.
-template <typename T, int KD, bool BK>
+template <typename T, int KD, bool BK, int TB = TPB>
 __device__ __forceinline__ void gemm_sub(T *A, int ld, int rowA, int rowEnd, int colA, int ncol, int kb,
                                          const T *Bs, int ldb, int bcol0) {
     ld = opaque_s(ld);
@@ -395,7 +395,7 @@ __device__ __forceinline__ void gemm_sub(T *A, int ld, int rowA, int rowEnd, int
     const int nrt = (rowEnd - rowA + 15) >> 4;
     const int nct = (ncol + 15) >> 4;
     if (nrt <= 0 || ncol <= 0) return;
-    for (int rt = wave; rt < nrt; rt += TPB / 64) {
+    for (int rt = wave; rt < nrt; rt += TB / 64) {
         const int r0 = rowA + 16 * rt;
         T af[KD / 4];
         const T *lcol = A + (size_t)kb * ld + r0 + i16;
@@ -434,11 +434,12 @@ __device__ __forceinline__ void gemm_sub(T *A, int ld, int rowA, int rowEnd, int
     }
 }
 
-// RMAX: largest number of rows per thread in a panel (n1 <= TPB * RMAX).
-// Up to three rows per thread two workgroups share a CU; the instance for
-// the largest systems (up to five) takes the whole register file of one.
-template <typename T, int NB, int RMAX>
-__global__ __launch_bounds__(TPB, RMAX <= 3 ? 2 : 1) void lu_kernel(WsView v, int32_t *__restrict__ info_out) {
+// TB threads (TB / 64 wavefronts) per airfoil; RMAX: largest number of rows
+// per thread in a panel (n1 <= TB * RMAX).  With 256 threads and up to three
+// rows per thread two workgroups share a CU; the other instances take the
+// whole register file of one.
+template <typename T, int NB, int RMAX, int TB>
+__global__ __launch_bounds__(TB, (TB <= 256 && RMAX <= 3) ? 2 : 1) void lu_kernel(WsView v, int32_t *__restrict__ info_out) {
     const int b = v.order[blockIdx.x];
     const AirfoilMeta mt = v.meta[b];
     const int n = mt.n1, ld = mt.ld, ncols = mt.n1 + mt.K;
@@ -447,14 +448,14 @@ __global__ __launch_bounds__(TPB, RMAX <= 3 ? 2 : 1) void lu_kernel(WsView v, in
 
     if (v.flag[b] != 0) {   // screened out by the assembly
         if (tid == 0) info_out[b] = -1;
-        for (int i = tid; i < n * mt.K; i += TPB) X[i] = __builtin_nan("");
+        for (int i = tid; i < n * mt.K; i += TB) X[i] = __builtin_nan("");
         return;
     }
 
     T *A = sys_base<T>(v, mt);
     int32_t *piv = v.piv + mt.piv_off;
 
-    __shared__ PanelLds<T, NB, RMAX> L;
+    __shared__ PanelLds<T, NB, RMAX, TB> L;
     __shared__ T s_L11[NB][NB + 1];
     __shared__ T s_U[NB][CH + 4];   // also holds the CT x (SP + 1) band of step 6
     int info = 0;
@@ -468,18 +469,18 @@ __global__ __launch_bounds__(TPB, RMAX <= 3 ? 2 : 1) void lu_kernel(WsView v, in
         const int nb = min(NB, n - k0);
 
         // ---- 1.-3. the panel: load, factorise, store ------------------------
-        const int rows = (n - k0 + TPB - 1) / TPB;
-        wg_panel_if<T, NB, 1>(rows, A, ld, n, k0, nb, piv, info, L, s_L11) ||
-            wg_panel_if<T, NB, (RMAX >= 2 ? 2 : 1)>(rows, A, ld, n, k0, nb, piv, info, L, s_L11) ||
-            wg_panel_if<T, NB, (RMAX >= 3 ? 3 : 1)>(rows, A, ld, n, k0, nb, piv, info, L, s_L11) ||
-            wg_panel_if<T, NB, (RMAX >= 4 ? 4 : 1)>(rows, A, ld, n, k0, nb, piv, info, L, s_L11) ||
-            wg_panel_if<T, NB, (RMAX >= 5 ? 5 : 1)>(rows, A, ld, n, k0, nb, piv, info, L, s_L11);
+        const int rows = (n - k0 + TB - 1) / TB;
+        wg_panel_if<T, NB, 1, TB>(rows, A, ld, n, k0, nb, piv, info, L, s_L11) ||
+            wg_panel_if<T, NB, (RMAX >= 2 ? 2 : 1), TB>(rows, A, ld, n, k0, nb, piv, info, L, s_L11) ||
+            wg_panel_if<T, NB, (RMAX >= 3 ? 3 : 1), TB>(rows, A, ld, n, k0, nb, piv, info, L, s_L11) ||
+            wg_panel_if<T, NB, (RMAX >= 4 ? 4 : 1), TB>(rows, A, ld, n, k0, nb, piv, info, L, s_L11) ||
+            wg_panel_if<T, NB, (RMAX >= 5 ? 5 : 1), TB>(rows, A, ld, n, k0, nb, piv, info, L, s_L11);
         __syncthreads();
 
         // ---- 4. the panel's row exchanges on every other column ------------
         // (each thread owns whole columns; exchanges are rare for this system,
         // so the sequential per-column loop costs little)
-        for (int j = tid; j < ncols - nb; j += TPB) {
+        for (int j = tid; j < ncols - nb; j += TB) {
             const int col = j < k0 ? j : j + nb;
             T *cp = A + (size_t)col * ld;
             for (int c = 0; c < nb; ++c) {
@@ -498,7 +499,7 @@ __global__ __launch_bounds__(TPB, RMAX <= 3 ? 2 : 1) void lu_kernel(WsView v, in
         if (rows0 < kend) {
             trsm_cols<T, NB>(A, ld, k0, nb, rows0, kend - rows0, s_L11, &s_U[0][0]);
             __syncthreads();
-            if (rows0 < n) gemm_sub<T, NB, true>(A, ld, rows0, n, rows0, kend - rows0, k0, &s_U[0][0], CH + 4, 0);
+            if (rows0 < n) gemm_sub<T, NB, true, TB>(A, ld, rows0, n, rows0, kend - rows0, k0, &s_U[0][0], CH + 4, 0);
             __syncthreads();
         }
     }
@@ -521,7 +522,7 @@ __global__ __launch_bounds__(TPB, RMAX <= 3 ? 2 : 1) void lu_kernel(WsView v, in
                 trsm_cols<T, NB>(A, ld, k0, nb, cs, cw, s_L11, &s_U[0][0]);
                 __syncthreads();
                 if (k0 + nb < kend)
-                    gemm_sub<T, NB, true>(A, ld, k0 + nb, kend, cs, cw, k0, &s_U[0][0], CH + 4, 0);
+                    gemm_sub<T, NB, true, TB>(A, ld, k0 + nb, kend, cs, cw, k0, &s_U[0][0], CH + 4, 0);
                 __syncthreads();
             }
         }
@@ -529,12 +530,12 @@ __global__ __launch_bounds__(TPB, RMAX <= 3 ? 2 : 1) void lu_kernel(WsView v, in
             T *Bs = &s_U[0][0];   // CT x SP band of U, column-major (ld SP+1)
             for (int cs = kend; cs < ncols; cs += CT) {
                 const int cw = min(CT, ncols - cs);
-                for (int idx = tid; idx < SP * CT; idx += TPB) {
+                for (int idx = tid; idx < SP * CT; idx += TB) {
                     const int c = idx / SP, r = idx - c * SP;
                     Bs[c * (SP + 1) + r] = (c < cw) ? A[(size_t)(cs + c) * ld + K0 + r] : T(0);
                 }
                 __syncthreads();
-                gemm_sub<T, SP, false>(A, ld, kend, n, cs, cw, K0, Bs, SP + 1, 0);
+                gemm_sub<T, SP, false, TB>(A, ld, kend, n, cs, cw, K0, Bs, SP + 1, 0);
                 __syncthreads();
             }
         }
@@ -548,17 +549,17 @@ __global__ __launch_bounds__(TPB, RMAX <= 3 ? 2 : 1) void lu_kernel(WsView v, in
         v.flag[b] = info;
     }
     if (info != 0) {
-        for (int i = tid; i < n * mt.K; i += TPB) X[i] = __builtin_nan("");
+        for (int i = tid; i < n * mt.K; i += TB) X[i] = __builtin_nan("");
         return;
     }
     __shared__ T y[PANEL_NMAX + 1];
     T *sblk = &s_U[0][0];   // SB x SB values (NB * CH >= SB * SB)
     for (int k = 0; k < mt.K; ++k) {
         __syncthreads();
-        for (int i = tid; i < n; i += TPB) y[i] = A[(size_t)(n + k) * ld + i];
+        for (int i = tid; i < n; i += TB) y[i] = A[(size_t)(n + k) * ld + i];
         __syncthreads();
-        trsv_upper<T, T>(A, ld, n, y, sblk);
-        for (int i = tid; i < n; i += TPB) X[(size_t)k * n + i] = (double)y[i];
+        trsv_upper<T, T, TB>(A, ld, n, y, sblk);
+        for (int i = tid; i < n; i += TB) X[(size_t)k * n + i] = (double)y[i];
     }
 }
 
@@ -723,13 +724,30 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
     }
 }
 
+// Compute units of the current device (read once per process and device).
+int device_cus() {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+        cus[dev] = c;
+    }
+    return cus[dev];
+}
+
+// With at most one airfoil per CU, eight wavefronts per airfoil (the whole
+// CU) beat four (measured: 256 sections at N = 1024, 24.4 -> 19.9 ms in
+// FP64); with more airfoils than CUs, four per airfoil and two airfoils per
+// CU keep more systems in flight (4096 airfoils, N = 96..512: 17.2 ms
+// against 22.6).  Systems of more than 768 rows always take eight.
 template <typename T>
 hipError_t launch_lu_any(const WsView &v, int32_t B, int32_t max_n1, int32_t *info, hipStream_t s) {
-    const int R = (max_n1 + TPB - 1) / TPB;
-    if (R <= 3)
-        lu_kernel<T, 16, 3><<<B, TPB, 0, s>>>(v, info);
+    if (B <= device_cus() || max_n1 > 3 * TPB)
+        lu_kernel<T, 16, 3, 512><<<B, 512, 0, s>>>(v, info);   // n1 <= 1536
     else
-        lu_kernel<T, 16, 5><<<B, TPB, 0, s>>>(v, info);
+        lu_kernel<T, 16, 3, TPB><<<B, TPB, 0, s>>>(v, info);
     return hipGetLastError();
 }
 
