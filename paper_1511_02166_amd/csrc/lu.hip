@@ -570,7 +570,8 @@ __global__ __launch_bounds__(TB, (TB <= 256 && RMAX <= 3) ? 2 : 1) void lu_kerne
 // ||A||_inf ||x||_inf (no further sweep can improve x); otherwise
 // d = U^{-1} L^{-1} P r in FP32, x += d, and stop once ||d||_inf <= tol
 // ||x||_inf.
-__global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restrict__ info, double tol,
+template <int TB>
+__global__ __launch_bounds__(TB) void refine_kernel(WsView v, int32_t *__restrict__ info, double tol,
                                                      int max_iter) {
     constexpr int KG = 2;
     const int b = v.order[blockIdx.x];
@@ -592,7 +593,7 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
     __shared__ double sr[KG][PANEL_NMAX + 1];
     __shared__ float sd[PANEL_NMAX + 1];
     __shared__ int perm[PANEL_NMAX + 1];
-    __shared__ double red[3][TPB / 64];
+    __shared__ double red[3][TB / 64];
     __shared__ float sblk[SB * SB];
     if (tid == 0) {
         for (int i = 0; i < n; ++i) perm[i] = i;
@@ -619,7 +620,7 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
         a0 = red[0][0];
         a1 = red[1][0];
         a2 = red[2][0];
-        for (int w = 1; w < TPB / 64; ++w) {
+        for (int w = 1; w < TB / 64; ++w) {
             a0 = fmax(a0, red[0][w]);
             a1 = fmax(a1, red[1][w]);
             a2 = fmax(a2, red[2][w]);
@@ -633,7 +634,7 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
     for (int k0 = 0; k0 < mt.K; k0 += KG) {
         const int kn = min(KG, mt.K - k0);
         for (int kk = 0; kk < kn; ++kk)
-            for (int i = tid; i < n; i += TPB) sx[kk][i] = X[(size_t)(k0 + kk) * n + i];
+            for (int i = tid; i < n; i += TB) sx[kk][i] = X[(size_t)(k0 + kk) * n + i];
         __syncthreads();
         bool conv[KG];
         int sweeps[KG];
@@ -648,7 +649,7 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
             for (int kk = 0; kk < KG; ++kk) all = all && conv[kk];
             if (all) break;
             double rowmax = 0.0;
-            for (int i = tid; i < n; i += TPB) {
+            for (int i = tid; i < n; i += TB) {
                 double s0 = A[(size_t)(n + k0) * ld + i];
                 double s1 = (kn > 1) ? A[(size_t)(n + k0 + 1) * ld + i] : 0.0;
                 double ra = 0.0;
@@ -682,7 +683,7 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
             for (int kk = 0; kk < KG; ++kk) {
                 if (conv[kk]) continue;
                 double rmax = 0.0, xmax = 0.0, unused = 0.0;
-                for (int i = tid; i < n; i += TPB) {
+                for (int i = tid; i < n; i += TB) {
                     rmax = fmax(rmax, fabs(sr[kk][i]));
                     xmax = fmax(xmax, fabs(sx[kk][i]));
                 }
@@ -691,12 +692,12 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
                     conv[kk] = true;
                     continue;
                 }
-                for (int i = tid; i < n; i += TPB) sd[i] = (float)sr[kk][perm[i]];
+                for (int i = tid; i < n; i += TB) sd[i] = (float)sr[kk][perm[i]];
                 __syncthreads();
-                trsv_lower_unit<float, float>(LU, ld, n, sd, sblk);
-                trsv_upper<float, float>(LU, ld, n, sd, sblk);
+                trsv_lower_unit<float, float, TB>(LU, ld, n, sd, sblk);
+                trsv_upper<float, float, TB>(LU, ld, n, sd, sblk);
                 double dmax = 0.0, xn = 0.0;
-                for (int i = tid; i < n; i += TPB) {
+                for (int i = tid; i < n; i += TB) {
                     const double d = (double)sd[i];
                     const double x1 = sx[kk][i] + d;
                     sx[kk][i] = x1;
@@ -714,7 +715,7 @@ __global__ __launch_bounds__(TPB) void refine_kernel(WsView v, int32_t *__restri
             worst = max(worst, sweeps[kk]);
         }
         for (int kk = 0; kk < kn; ++kk)
-            for (int i = tid; i < n; i += TPB) X[(size_t)(k0 + kk) * n + i] = sx[kk][i];
+            for (int i = tid; i < n; i += TB) X[(size_t)(k0 + kk) * n + i] = sx[kk][i];
         __syncthreads();
     }
     if (tid == 0) {
@@ -766,7 +767,11 @@ hipError_t launch_factor_solve(const WsView &v, int32_t B, int32_t n_block, int3
     if (e != hipSuccess) return e;
     if (mixed) {
         if (n_block > 0) {
-            refine_kernel<<<n_block, TPB, 0, stream>>>(v, info, tol, max_iter);
+            // the same choice of workgroup size as for the factorisation
+            if (n_block <= device_cus() || max_n1_block > 3 * TPB)
+                refine_kernel<512><<<n_block, 512, 0, stream>>>(v, info, tol, max_iter);
+            else
+                refine_kernel<TPB><<<n_block, TPB, 0, stream>>>(v, info, tol, max_iter);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
