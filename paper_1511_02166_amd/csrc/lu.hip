@@ -3,13 +3,14 @@
 //
 // Sec. 3 of the paper: each airfoil needs an LU decomposition of its dense
 // system ((2/3)n^3 operations), and many small systems are solved at once.
-// One workgroup (4 waves) factors one airfoil's augmented matrix [M | rhs]
-// in place, right-looking and blocked by NB columns:
+// One workgroup (four wavefronts, or eight when the batch leaves at most one
+// airfoil per CU) factors one airfoil's augmented matrix [M | rhs] in place,
+// right-looking and blocked by NB columns:
 //   1. the n - k0 rows of the NB-column panel are held in registers, one row
 //      per thread; each column step finds the pivot with a wavefront
-//      shuffle reduction plus a 4-entry LDS reduction (largest |a|, lowest
-//      row index on ties), exchanges the two rows through LDS, scales and
-//      applies the rank-1 update to the thread's own rows;
+//      shuffle reduction plus an LDS reduction over the wavefronts (largest
+//      |a|, lowest row index on ties), exchanges the two rows through LDS,
+//      scales and applies the rank-1 update to the thread's own rows;
 //   2. the row exchanges are applied to every other column (each thread
 //      owns whole columns, so the exchanges of one panel run sequentially
 //      per column without synchronisation);
@@ -19,7 +20,7 @@
 // The right-hand-side columns ride along as extra columns, so after the
 // factorisation they hold L^{-1} P b; the same workgroup then finishes with
 // the back substitution (blocked: one wavefront solves each 64-row diagonal
-// block with shuffles, all four update the rows above).
+// block with shuffles, all of them update the rows above).
 #include <climits>
 
 #include "panel_internal.hpp"
@@ -28,7 +29,7 @@
 namespace panel {
 namespace {
 
-constexpr int TPB = 256;   // threads per workgroup (4 wavefronts)
+constexpr int TPB = 256;   // threads per workgroup by default (4 wavefronts)
 constexpr int CH = 256;    // trailing columns per U12 chunk
 constexpr int SB = 64;     // rows per diagonal block in the triangular solves
 constexpr int SP = 64;     // super-panel width (rank of the big trailing update)
