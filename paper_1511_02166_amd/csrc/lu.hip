@@ -34,6 +34,7 @@ constexpr int CH = 256;    // trailing columns per U12 chunk
 constexpr int SB = 64;     // rows per diagonal block in the triangular solves
 constexpr int SP = 64;     // super-panel width (rank of the big trailing update)
 constexpr int CT = 64;     // columns per LDS chunk of the rank-SP update
+constexpr int JR = 16;     // columns per round trip in the refinement residual
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
@@ -654,20 +655,22 @@ __global__ __launch_bounds__(TB) void refine_kernel(WsView v, int32_t *__restric
                 double s0 = A[(size_t)(n + k0) * ld + i];
                 double s1 = (kn > 1) ? A[(size_t)(n + k0 + 1) * ld + i] : 0.0;
                 double ra = 0.0;
-                if (anrm < 0.0) {
-                    for (int j = 0; j < n; ++j) {
-                        const double a = A[(size_t)j * ld + i];
-                        s0 -= a * sx[0][j];
-                        if (kn > 1) s1 -= a * sx[1][j];
-                        ra += fabs(a);
-                    }
-                } else if (kn == 1) {
-                    for (int j = 0; j < n; ++j) s0 -= A[(size_t)j * ld + i] * sx[0][j];
-                } else {
-                    for (int j = 0; j < n; ++j) {
-                        const double a = A[(size_t)j * ld + i];
-                        s0 -= a * sx[0][j];
-                        s1 -= a * sx[1][j];
+                const bool first_pass = anrm < 0.0;
+                // JR columns per round trip: all their loads are issued
+                // before the first product (left to itself the compiler put
+                // a wait after every load, one memory latency per element)
+                for (int j0 = 0; j0 < n; j0 += JR) {
+                    double a[JR];
+#pragma unroll
+                    for (int jj = 0; jj < JR; ++jj) a[jj] = A[(size_t)min(j0 + jj, n - 1) * ld + i];
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int jj = 0; jj < JR; ++jj) {
+                        if (j0 + jj < n) {
+                            s0 -= a[jj] * sx[0][j0 + jj];
+                            if (kn > 1) s1 -= a[jj] * sx[1][j0 + jj];
+                            if (first_pass) ra += fabs(a[jj]);
+                        }
                     }
                 }
                 sr[0][i] = s0;

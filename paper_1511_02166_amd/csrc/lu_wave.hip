@@ -691,6 +691,7 @@ __device__ __forceinline__ void wave_max3(double &a, double &b, double &c) {
 __global__ __launch_bounds__(WL, 2) void refine_wave_kernel(WsView v, int32_t first, int32_t *__restrict__ info,
                                                          double tol, int max_iter) {
     constexpr int RM = PANEL_WAVE_RMAX;
+    constexpr int JB = 4;
     const int b = v.order[first + blockIdx.x];
     const AirfoilMeta mt = v.meta[b];
     const int n = mt.n1, ld = mt.ld;
@@ -737,24 +738,29 @@ __global__ __launch_bounds__(WL, 2) void refine_wave_kernel(WsView v, int32_t fi
                 rs[q] = A[(size_t)(n + k) * ld + r];
                 ra[q] = 0.0;
             }
-            if (anrm < 0.0) {
-                for (int j = 0; j < n; ++j) {
-                    const double xj = sx[j];
-                    const double *col = A + (size_t)j * ld + lane;
+            // JB columns per round trip: all their loads are issued before
+            // the first product (left to itself the compiler placed a wait
+            // after every load, one memory latency per element)
+            const bool first_pass = anrm < 0.0;
+            for (int j0 = 0; j0 < n; j0 += JB) {
+                double a[JB][RM];
 #pragma unroll
-                    for (int q = 0; q < RM; ++q) {
-                        const double a = col[min(WL * q, n - 1 - lane)];
-                        rs[q] -= a * xj;
-                        ra[q] += fabs(a);
-                    }
+                for (int jj = 0; jj < JB; ++jj) {
+                    const double *col = A + (size_t)min(j0 + jj, n - 1) * ld + lane;
+#pragma unroll
+                    for (int q = 0; q < RM; ++q) a[jj][q] = col[min(WL * q, n - 1 - lane)];
                 }
-            } else {
-#pragma unroll 4
-                for (int j = 0; j < n; ++j) {
-                    const double xj = sx[j];
-                    const double *col = A + (size_t)j * ld + lane;
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int q = 0; q < RM; ++q) rs[q] -= col[min(WL * q, n - 1 - lane)] * xj;
+                for (int jj = 0; jj < JB; ++jj) {
+                    if (j0 + jj < n) {
+                        const double xj = sx[j0 + jj];
+#pragma unroll
+                        for (int q = 0; q < RM; ++q) {
+                            rs[q] -= a[jj][q] * xj;
+                            if (first_pass) ra[q] += fabs(a[jj][q]);
+                        }
+                    }
                 }
             }
             double rmax = 0.0, xmax = 0.0, rowmax = 0.0;
