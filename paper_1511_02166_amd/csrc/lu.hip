@@ -87,6 +87,27 @@ __device__ inline bool better(double va, int ia, double vb, int ib) {
 // broadcast through a scalar register; the other rows are then updated by
 // the whole workgroup.
 
+// s - sum_{j < SB} p[j ld] yb[j] for one row of a full 64-column block:
+// loads in groups of 16 issued before their products (left to itself the
+// compiler waited after every load).
+template <typename T, typename V>
+__device__ __forceinline__ V block_dot(const T *p, int ld, const V *yb, V s) {
+    V s1 = V(0);
+#pragma unroll
+    for (int j0 = 0; j0 < SB; j0 += 16) {
+        T a[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) a[jj] = p[(size_t)(j0 + jj) * ld];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int jj = 0; jj < 16; jj += 2) {
+            s -= V(a[jj]) * yb[j0 + jj];
+            s1 -= V(a[jj + 1]) * yb[j0 + jj + 1];
+        }
+    }
+    return s + s1;
+}
+
 // Back substitution U x = y (U upper, column-major in global memory), y in LDS.
 template <typename T, typename V, int TB = TPB>
 __device__ void trsv_upper(const T *U, int ld, int n, V *y, T *sblk) {
@@ -113,13 +134,7 @@ __device__ void trsv_upper(const T *U, int ld, int n, V *y, T *sblk) {
         for (int r = tid; r < rb; r += TB) {
             const T *up = U + (size_t)rb * ld + r;
             if (w == SB) {   // every block but the last, partial one
-                V s0 = y[r], s1 = V(0);
-#pragma unroll 16
-                for (int j = 0; j < SB; j += 2) {
-                    s0 -= V(up[(size_t)j * ld]) * y[rb + j];
-                    s1 -= V(up[(size_t)(j + 1) * ld]) * y[rb + j + 1];
-                }
-                y[r] = s0 + s1;
+                y[r] = block_dot<T, V>(up, ld, y + rb, y[r]);
             } else {
                 V s = y[r];
                 for (int j = 0; j < w; ++j) s -= V(up[(size_t)j * ld]) * y[rb + j];
@@ -153,14 +168,7 @@ __device__ void trsv_lower_unit(const T *L, int ld, int n, V *y, T *sblk) {
         __syncthreads();
         for (int r = rb + w + tid; r < n; r += TB) {
             // rows below a block exist only when the block is full (w == SB)
-            V s0 = y[r], s1 = V(0);
-            const T *lp = L + (size_t)rb * ld + r;
-#pragma unroll 16
-            for (int j = 0; j < SB; j += 2) {
-                s0 -= V(lp[(size_t)j * ld]) * y[rb + j];
-                s1 -= V(lp[(size_t)(j + 1) * ld]) * y[rb + j + 1];
-            }
-            y[r] = s0 + s1;
+            y[r] = block_dot<T, V>(L + (size_t)rb * ld + r, ld, y + rb, y[r]);
         }
         __syncthreads();
     }
