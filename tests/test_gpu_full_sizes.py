@@ -173,3 +173,23 @@ def test_adjoint_full_batch(name, sample):
         e = np.max(np.abs(gb - ref)) / np.max(np.abs(ref))
         _say(f"  airfoil {b}: gradient rel err {e:.2e}")
         assert e < (1e-9 if w.n_panels[b] <= 512 else 1e-8), (b, e)
+
+
+def _mid_size_workload(B, seed):
+    """B NACA sections with N in [600, 760] (system order 601..761): more
+    airfoils than CUs and rows up to three per thread of a four-wavefront
+    workgroup."""
+    rng = np.random.default_rng(seed)
+    m, p, t = synth._naca_draws(rng, B)
+    n = (2 * rng.integers(300, 381, B)).astype(np.int32)
+    alpha = [np.array([rng.uniform(-4.0, 10.0) * synth.DEG]) for _ in range(B)]
+    return synth.Workload("mid", m, p, t, n, alpha, True, {"seed": seed})
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mid_size_batch_more_airfoils_than_cus(precision):
+    w = _mid_size_workload(300, 12)
+    _say(f"mid-size batch: {w.B} airfoils, N in [{w.n_panels.min()}, {w.n_panels.max()}], precision={precision}")
+    s, _, got = _run_full(w, precision)
+    _check_batch_properties(w, got, precision)
+    _check_sample(w, got, _sample(w, 3, 13), precision)
