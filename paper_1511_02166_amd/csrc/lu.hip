@@ -312,15 +312,21 @@ __device__ __forceinline__ void wg_panel(T *A, int ld, int n, int k0, int nb, in
     ld = opaque_s(ld);
     const int tid = threadIdx.x;
     T p[R][NB];
+    // every load is issued (clamped addresses) before any is masked: with
+    // the mask next to the load the compiler put each load in a branch of
+    // its own and waited for it there, one memory latency per element
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int rr = min(k0 + tid + TB * q, n - 1);
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) p[q][cc] = A[(size_t)min(k0 + cc, n - 1) * ld + rr];
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int r = k0 + tid + TB * q;
-        const int rr = r < n ? r : n - 1;
 #pragma unroll
-        for (int cc = 0; cc < NB; ++cc) {
-            const T t = A[(size_t)min(k0 + cc, n - 1) * ld + rr];
-            p[q][cc] = (r < n && cc < nb) ? t : T(0);
-        }
+        for (int cc = 0; cc < NB; ++cc) p[q][cc] = (r < n && cc < nb) ? p[q][cc] : T(0);
     }
     panel_steps<T, NB, R, 0, TB>(p, k0, nb, n, info, L);
     __syncthreads();

@@ -407,17 +407,23 @@ __device__ __forceinline__ void wave_panel(T *A, int ld, int n, int k0, int nb, 
     T p[R][WNB];
     int pos[R];
     unsigned live = 0;
+    // every load is issued (clamped addresses) before any is masked: with
+    // the mask next to the load the compiler put each load in a branch of
+    // its own and waited for it there, one memory latency per element
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int rr = min(k0 + lane + WL * q, n - 1);
+#pragma unroll
+        for (int cc = 0; cc < WNB; ++cc) p[q][cc] = A[(size_t)(k0 + min(cc, nb - 1)) * ld + rr];
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int r = k0 + lane + WL * q;
         pos[q] = r;
         if (r < n) live |= 1u << q;
-        const int rr = r < n ? r : n - 1;
 #pragma unroll
-        for (int cc = 0; cc < WNB; ++cc) {
-            const T t = A[(size_t)(k0 + min(cc, nb - 1)) * ld + rr];
-            p[q][cc] = (r < n && cc < nb) ? t : T(0);
-        }
+        for (int cc = 0; cc < WNB; ++cc) p[q][cc] = (r < n && cc < nb) ? p[q][cc] : T(0);
     }
     if (lane < WNB) {
 #pragma unroll
