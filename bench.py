@@ -39,7 +39,7 @@ ASM_FLOPS_PER_ENTRY = 118.0
 # batch, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's
 # readings (x2.0 and x1.0).  Valid only for the kernel source it was taken
 # on, which is identified by the SHA-256 prefix of that source file.
-LU_TRAFFIC = {("lu_wave.hip", "e419325668ac2d9d"): 10_234_022_224}   # one wavefront per airfoil
+LU_TRAFFIC = {("lu_wave.hip", "2e2fbcc78dbaeca4"): 10_219_450_864}   # one wavefront per airfoil
 
 
 def _args():
