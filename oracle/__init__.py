@@ -18,6 +18,9 @@ Parity status per function (see the pins under ``tests/``):
                         sections at zero incidence, the paper's C_L tables)
   oracle_cl_gradient    pinned (central differences, exact discrete
                         invariants: translation, scaling, rotation)
+  oracle_force_gradient pinned (central differences of the oracle's Cp and
+                        Cl; translation, scaling and rotation invariants of
+                        Cp; equals oracle_cl_gradient without cp weights)
 """
 from __future__ import annotations
 
@@ -87,6 +90,9 @@ def lib():
             L.oracle_naca4_jacobian.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int,
                                                 C.c_int, _dp]
             L.oracle_naca4_jacobian.restype = None
+            L.oracle_force_gradient.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_double,
+                                                C.c_double, C.c_void_p, _dp]
+            L.oracle_force_gradient.restype = C.c_int
         _lib = L
     return _lib
 
@@ -215,6 +221,23 @@ def cl_gradient(xy, alpha, vinf=1.0, chord=1.0, with_alpha=False):
         raise RuntimeError(f"oracle gradient failed, info={info}")
     if with_alpha:
         return g.reshape(N + 1, 2), float(da[0])
+    return g.reshape(N + 1, 2)
+
+
+def force_gradient(xy, alpha, dcl=1.0, dcp=None, vinf=1.0, chord=1.0):
+    """d/dP of dcl * Cl + sum_i dcp[i] Cp_i for one angle: [N+1, 2]."""
+    xy = _f64(xy).reshape(-1)
+    N = xy.size // 2 - 1
+    g = np.zeros(2 * (N + 1))
+    w = None
+    if dcp is not None:
+        w = _f64(dcp).reshape(-1)
+        if w.size != N:
+            raise ValueError("dcp must hold one value per panel")
+    info = lib().oracle_force_gradient(N, xy, float(alpha), float(vinf), float(chord), float(dcl),
+                                       None if w is None else w.ctypes.data_as(C.c_void_p), g)
+    if info != 0:
+        raise RuntimeError(f"oracle gradient failed, info={info}")
     return g.reshape(N + 1, 2)
 
 

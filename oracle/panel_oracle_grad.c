@@ -202,3 +202,72 @@ void oracle_naca4_jacobian(double m, double p, double t, int N, int closed_te, d
         }
     }
 }
+
+/* Gradient of the weighted forces of one angle of attack,
+ *     F = dcl * Cl + sum_i dcp[i] * Cp_i,   Cp_i = 1 - (x_i / vinf)^2,
+ * with respect to every node coordinate (grad[2k + c], k = 0..N), by the
+ * same tangent-linear sweep as oracle_cl_gradient: per coordinate,
+ * dx = M^{-1}(dr - dM x), then dCl as above and dCp_i = -2 x_i dx_i / vinf^2.
+ * dcp may be NULL (then F is dcl * Cl).  Returns the LU info.              */
+int oracle_force_gradient(int N, const double *xy, double alpha, double vinf, double chord, double dcl,
+                          const double *dcp, double *grad)
+{
+    const int n1 = N + 1;
+    const int nc = 2 * (N + 1);
+    double *M = malloc(sizeof(double) * (size_t)n1 * n1);
+    double *x = malloc(sizeof(double) * (size_t)n1);
+    double *v = malloc(sizeof(double) * (size_t)n1);
+    int *piv = malloc(sizeof(int) * (size_t)n1);
+    double complex *z = malloc(sizeof(double complex) * (size_t)nc);
+    oracle_assemble(N, xy, 1, &alpha, vinf, M, x);
+    int info = oracle_lu(n1, M, piv);
+    if (info != 0)
+        goto done;
+    oracle_lu_solve(n1, M, piv, 1, x);
+    for (int q = 0; q < nc; ++q)
+        z[q] = xy[q];
+    const double ca = cos(alpha), sa = sin(alpha);
+    const double scale = -2.0 / (vinf * chord);
+
+    for (int q = 0; q < nc; ++q) {
+        const int k = q / 2;
+        const int c = q % 2;
+        z[q] = xy[q] + I * OG_H;
+        int lo = k - 1 < 0 ? 0 : k - 1;
+        int hi = k > N - 1 ? N - 1 : k;
+        for (int j = 0; j < n1; ++j)
+            v[j] = 0.0;
+        for (int j = lo; j <= hi; ++j)
+            v[j] = c == 0 ? vinf * sa * 0.5 : -vinf * ca * 0.5;
+        for (int j = 0; j < N; ++j) {
+            int row_moves = (j >= lo && j <= hi);
+            for (int i = 0; i < N; ++i) {
+                int col_moves = (i >= lo && i <= hi);
+                if (!row_moves && !col_moves)
+                    continue;
+                v[j] -= cimag(g_entry_c(z, j, i)) / OG_H * x[i];
+            }
+        }
+        oracle_lu_solve(n1, M, piv, 1, v);
+        double dcl_q = 0.0, dcp_q = 0.0;
+        for (int i = 0; i < N; ++i) {
+            double dL = 0.0;
+            if (i >= lo && i <= hi) {
+                double complex hx = z[2 * i + 2] - z[2 * i], hy = z[2 * i + 3] - z[2 * i + 1];
+                dL = cimag(csqrt(hx * hx + hy * hy)) / OG_H;
+            }
+            dcl_q += v[i] * panel_len(xy, i) + x[i] * dL;
+            if (dcp)
+                dcp_q += dcp[i] * (-2.0 * x[i] * v[i] / (vinf * vinf));
+        }
+        grad[q] = dcl * scale * dcl_q + dcp_q;
+        z[q] = xy[q];
+    }
+done:
+    free(M);
+    free(x);
+    free(v);
+    free(piv);
+    free(z);
+    return info;
+}

@@ -286,12 +286,75 @@ def test_scale_translation_rotation_invariance():
     r = oracle.solve_airfoil(xy * s + np.array([0.3, -0.8]), [a], chord=s)
     assert np.max(np.abs(r["gamma"] - base["gamma"])) < 1e-10
     assert abs(r["cl"][0] - base["cl"][0]) < 1e-12
+    assert abs(r["cl_p"][0] - base["cl_p"][0]) < 1e-11
     # rotating the section by beta (CCW) equals reducing the incidence by beta
     beta = 2.5 * DEG
     Rm = np.array([[np.cos(beta), -np.sin(beta)], [np.sin(beta), np.cos(beta)]])
     r = oracle.solve_airfoil(xy @ Rm.T, [a + beta])
     assert abs(r["cl"][0] - base["cl"][0]) < 1e-12
     assert abs(r["cl_p"][0] - base["cl_p"][0]) < 1e-11
+
+
+def test_lifting_cylinder_pressure_lift():
+    # The pressure integral of the lifting cylinder (Kutta point at theta = 0,
+    # chord 2R = 1) tends to the Kutta-Joukowski value 4 pi sin a at second
+    # order: pins the sign, the outward normal and e_L in Cl_p.
+    a = 5 * DEG
+    errs = []
+    for N in (64, 128, 256):
+        r = oracle.solve_airfoil(synth.circle_nodes(N, R=0.5), [a], chord=1.0)
+        errs.append(abs(r["cl_p"][0] - 4 * np.pi * np.sin(a)))
+    assert errs[2] < 2e-4
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
+
+
+def test_freestream_speed_and_chord_scaling():
+    # The system is linear in vinf (right-hand side only): gamma scales with
+    # vinf, while Cp = 1 - (gamma/vinf)^2, Cl and Cl_p do not change.  The
+    # chord c only normalises the two lift coefficients (both ~ 1/c).
+    xy = oracle.naca4(0.03, 0.35, 0.11, 96)
+    a = [6 * DEG, -2 * DEG]
+    base = oracle.solve_airfoil(xy, a)
+    v = 2.5
+    r = oracle.solve_airfoil(xy, a, vinf=v)
+    assert np.max(np.abs(r["gamma"] - v * base["gamma"])) < 1e-12 * v * np.max(np.abs(base["gamma"])) * 10
+    assert np.max(np.abs(r["cp"] - base["cp"])) < 1e-12
+    assert np.max(np.abs(r["cl"] - base["cl"])) < 1e-13
+    assert np.max(np.abs(r["cl_p"] - base["cl_p"])) < 1e-13
+    c = 0.37
+    r = oracle.solve_airfoil(xy, a, vinf=v, chord=c)
+    assert np.max(np.abs(c * r["cl"] - base["cl"])) < 1e-13
+    assert np.max(np.abs(c * r["cl_p"] - base["cl_p"])) < 1e-13
+    assert np.max(np.abs(r["gamma"] - v * base["gamma"])) < 1e-11
+
+
+def test_batch_packing_matches_single_airfoil_calls():
+    # The batch entry point packs every airfoil's outputs at offsets derived
+    # from (N_b, K_b); per-airfoil chords and a common vinf.  Each slice must
+    # equal the one-airfoil call bit for bit (same arithmetic, same order),
+    # with the offsets recomputed here from the panel and angle counts.
+    rng = np.random.default_rng(41)
+    Ns = [16, 40, 6, 64, 30]
+    Ks = [1, 3, 4, 2, 1]
+    nodes = [oracle.naca4(rng.uniform(0, 0.06), rng.uniform(0.2, 0.6), rng.uniform(0.08, 0.18), n)
+             for n in Ns]
+    xy, noff = synth.pack_nodes(nodes)
+    alphas = [rng.uniform(-4, 12, k) * DEG for k in Ks]
+    aoff = np.concatenate([[0], np.cumsum(Ks)]).astype(np.int32)
+    chord = rng.uniform(0.5, 2.0, len(Ns))
+    vinf = 1.7
+    r = oracle.solve_batch(xy, noff, np.concatenate(alphas), aoff, chord=chord, vinf=vinf, nthreads=2)
+    assert np.all(r["info"] == 0)
+    so = 0
+    for b, (N, K) in enumerate(zip(Ns, Ks)):
+        assert noff[b + 1] - noff[b] == N + 1
+        one = oracle.solve_airfoil(nodes[b], alphas[b], vinf=vinf, chord=chord[b])
+        assert np.array_equal(r["gamma"][so:so + N * K], one["gamma"].reshape(-1))
+        assert np.array_equal(r["cp"][so:so + N * K], one["cp"].reshape(-1))
+        assert np.array_equal(r["cl"][aoff[b]:aoff[b + 1]], one["cl"])
+        assert np.array_equal(r["cl_p"][aoff[b]:aoff[b + 1]], one["cl_p"])
+        so += N * K
+    assert so == r["gamma"].size
 
 
 def test_panel_refinement_cauchy_and_pressure_lift_agree():
@@ -366,3 +429,48 @@ def test_paper_lift_table_2000_panels():
     i = g["panels"].index(2000)
     xy = oracle.naca4(0.02, 0.4, 0.12, 2000, closed_te=False, uniform=True)
     assert abs(oracle.solve_airfoil(xy, [0.0])["cl"][0] - g["cl"][i]) < 5e-4
+
+
+def _weighted_forces(xy, a, dcl, dcp, vinf=1.0, chord=1.0):
+    r = oracle.solve_airfoil(xy, [a], vinf=vinf, chord=chord)
+    return dcl * r["cl"][0] + float(np.dot(dcp, r["cp"][0]))
+
+
+def test_force_gradient_vs_central_differences():
+    # d/dP of dcl Cl + sum_i dcp_i Cp_i against central differences of the
+    # oracle's own forward solve (vinf and chord away from 1).
+    N, a, h, vinf, chord = 24, 5 * DEG, 1e-6, 1.6, 0.8
+    xy = oracle.naca4(0.04, 0.35, 0.13, N)
+    rng = np.random.default_rng(5)
+    dcp = rng.standard_normal(N)
+    dcl = 0.7
+    g = oracle.force_gradient(xy, a, dcl, dcp, vinf=vinf, chord=chord)
+    fd = np.zeros_like(xy)
+    for k in range(N + 1):
+        for c in range(2):
+            p, m = xy.copy(), xy.copy()
+            p[k, c] += h
+            m[k, c] -= h
+            fd[k, c] = (_weighted_forces(p, a, dcl, dcp, vinf, chord) -
+                        _weighted_forces(m, a, dcl, dcp, vinf, chord)) / (2 * h)
+    assert np.max(np.abs(g - fd)) < 1e-6 * np.max(np.abs(fd))
+    # without pressure weights it is the lift gradient
+    assert np.max(np.abs(oracle.force_gradient(xy, a, 1.0, None, vinf, chord) -
+                         oracle.cl_gradient(xy, a, vinf, chord))) == 0.0
+
+
+def test_force_gradient_pressure_invariants():
+    # Cp_i is invariant under translation and uniform scaling of the nodes
+    # (gamma is), so its node gradient sums to zero and is orthogonal to P;
+    # a rotation by beta equals an incidence change of -beta.
+    N, a = 96, 3 * DEG
+    xy = oracle.naca4(0.02, 0.45, 0.14, N)
+    dcp = np.random.default_rng(6).standard_normal(N)
+    g = oracle.force_gradient(xy, a, 0.0, dcp)
+    scale = np.max(np.abs(g))
+    assert np.max(np.abs(g.sum(0))) < 1e-9 * scale
+    assert abs((xy * g).sum()) < 1e-9 * scale * np.max(np.abs(xy))
+    h = 1e-6
+    dfa = (_weighted_forces(xy, a + h, 0.0, dcp) - _weighted_forces(xy, a - h, 0.0, dcp)) / (2 * h)
+    perp = np.stack([-xy[:, 1], xy[:, 0]], 1)
+    assert abs((perp * g).sum() + dfa) < 1e-6 * max(1.0, abs(dfa))
