@@ -5,19 +5,25 @@ One step = one pass of the panel-method hot path over the whole batch:
 assembly (FP64) -> LU with partial pivoting + solve (FP64, or FP32 factors
 with FP64 iterative refinement) -> surface speed / Cp / Cl reductions.
 Inputs (NACA nodes from the library's geometry kernel, angles) are resident
-in device memory before the timed region starts.
+in device memory before the timed region starts.  The timed step is one
+replay of a HIP graph that holds the three calls (the same kernels the
+eager calls launch); an eager pass with events between the calls gives the
+per-kernel breakdown and the roofline figures.
 
 Prints ONE JSON line.  ``value`` is the FP64 solves/s on the GA-population
 batch (2048 seeded NACA 4-digit airfoils, 256 panels, 257x257 systems);
-the FP32+refinement rate, the adjoint rate, per-kernel times, the roofline
-of the dominant kernel and the CPU oracle baseline ride along.
+the FP32+refinement rate, the adjoint rate (1024 airfoils at 6 degrees),
+per-kernel times, the roofline of every hot kernel, the uneven and
+large-panel batches and the CPU oracle baseline ride along.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import platform
+import statistics
+import subprocess
 import sys
 import time
 
@@ -39,7 +45,10 @@ ASM_FLOPS_PER_ENTRY = 118.0
 # batch, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's
 # readings (x2.0 and x1.0).  Valid only for the kernel source it was taken
 # on, which is identified by the SHA-256 prefix of that source file.
-LU_TRAFFIC = {("lu_wave.hip", "2e2fbcc78dbaeca4"): 10_219_450_864}   # one wavefront per airfoil
+LU_TRAFFIC = {}
+
+# Host threads for the oracle: the box assigns 16 host cores to each GPU.
+CPU_SHARE = 16
 
 
 def _args():
@@ -52,20 +61,35 @@ def _args():
     ap.add_argument("--batch", type=int, default=None, help="truncate the batch (debugging only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=None,
-                    help="airfoils in the oracle sample (default: the whole batch)")
+                    help="airfoils in the all-core oracle sample (default: the whole batch)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-side", action="store_true", help="skip the uneven and large-panel batches")
+    ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of a graph replay")
     ap.add_argument("--wave-limit", type=int, default=None,
                     help="largest system order for the one-wavefront LU (0 = workgroup LU only)")
     return ap.parse_args()
 
 
-def _flops(w):
+def _work(w):
     n1 = w.n_panels.astype(np.float64) + 1
     K = np.array([len(a) for a in w.alpha], dtype=np.float64)
     lu = float(np.sum(2.0 / 3.0 * n1 ** 3))
     solve = float(np.sum(2.0 * n1 ** 2 * K))
     pairs = float(np.sum(w.n_panels.astype(np.float64) ** 2))
     return lu, solve, pairs
+
+
+def _cpu_info():
+    info = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "machine": platform.machine()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core"):
+                info[k.strip()] = v.strip()
+    except Exception:
+        pass
+    return info
 
 
 def main():
@@ -83,31 +107,24 @@ def main():
         sys.exit(1)
     P.load_library()   # fails loudly without the HIP library
     dev = torch.device("cuda")
-    w = synth.workload(a.workload, B=a.batch)
-    noff, aoff = w.node_offsets(), w.alpha_offsets()
-    alpha = torch.as_tensor(w.alpha_flat(), device=dev)
-    mpt = torch.as_tensor(w.mpt(), device=dev)
+    stream = torch.cuda.current_stream()
 
-    s64 = P.PanelSolver(noff, aoff, P.PANEL_FP64, wave_limit=a.wave_limit)
-    s32 = P.PanelSolver(noff, aoff, P.PANEL_FP32_REFINE, wave_limit=a.wave_limit)
-    xy = s64.naca4(mpt, True)
-    torch.cuda.synchronize()
+    def setup(name, batch=None, wave_limit=None):
+        w = synth.workload(name, B=batch)
+        noff, aoff = w.node_offsets(), w.alpha_offsets()
+        alpha = torch.as_tensor(w.alpha_flat(), device=dev)
+        s64 = P.PanelSolver(noff, aoff, P.PANEL_FP64, wave_limit=wave_limit)
+        s32 = P.PanelSolver(noff, aoff, P.PANEL_FP32_REFINE, wave_limit=wave_limit)
+        xy = s64.naca4(torch.as_tensor(w.mpt(), device=dev), True)
+        torch.cuda.synchronize()
+        return w, xy, alpha, s64, s32
 
-    lu_f, solve_f, pairs = _flops(w)
-    B = w.B
-    n_solves = int(aoff[-1])
-
-    def timed(solver, steps, warmup, tol=1e-10, max_iter=10):
-        stream = torch.cuda.current_stream()
+    def eager(solver, xy, alpha, steps, warmup, tol=1e-10, max_iter=10):
+        """Per-call times from events between the three calls."""
         for _ in range(warmup):
             solver.step(xy, alpha, refine_tol=tol, max_iter=max_iter)
         torch.cuda.synchronize()
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
-        t_start = torch.cuda.Event(enable_timing=True)
-        t_end = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        wall0 = time.perf_counter()
-        t_start.record(stream)
         for i in range(steps):
             e = ev[i]
             e[0].record(stream)
@@ -117,76 +134,151 @@ def main():
             e[2].record(stream)
             solver.forces(True)
             e[3].record(stream)
-        t_end.record(stream)
+        torch.cuda.synchronize()
+        return dict(assemble_ms=float(np.mean([e[0].elapsed_time(e[1]) for e in ev])),
+                    factor_solve_ms=float(np.mean([e[1].elapsed_time(e[2]) for e in ev])),
+                    forces_ms=float(np.mean([e[2].elapsed_time(e[3]) for e in ev])),
+                    eager_ms_per_step=float(np.mean([e[0].elapsed_time(e[3]) for e in ev])))
+
+    def replay(solver, xy, alpha, steps, warmup, use_graph=True, tol=1e-10, max_iter=10):
+        """Whole-step time: graph replays (or eager steps) between two events."""
+        run = lambda: solver.step(xy, alpha, refine_tol=tol, max_iter=max_iter)
+        if use_graph:
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(stream)
+            with torch.cuda.stream(side):
+                run()                                    # warm the side stream
+                with torch.cuda.graph(g, stream=side):
+                    run()
+            stream.wait_stream(side)
+            torch.cuda.synchronize()
+            run = g.replay
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        wall0 = time.perf_counter()
+        t0.record(stream)
+        for _ in range(steps):
+            run()
+        t1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
-        total_ms = t_start.elapsed_time(t_end)
-        asm = np.mean([e[0].elapsed_time(e[1]) for e in ev])
-        fs = np.mean([e[1].elapsed_time(e[2]) for e in ev])
-        fo = np.mean([e[2].elapsed_time(e[3]) for e in ev])
-        return dict(ms_per_step=total_ms / steps, wall_ms_per_step=1e3 * wall / steps,
-                    assemble_ms=float(asm), factor_solve_ms=float(fs), forces_ms=float(fo))
+        return dict(ms_per_step=t0.elapsed_time(t1) / steps, wall_ms_per_step=1e3 * wall / steps,
+                    timing="hip graph replay" if use_graph else "eager calls")
 
-    r64 = timed(s64, a.steps, a.warmup)
-    info64 = s64.info.cpu().numpy()
-    cl64 = s64.cl.cpu().numpy()
-    cp64 = s64.cp.cpu().numpy()
-    r32 = timed(s32, a.steps, a.warmup)
-    info32 = s32.info.cpu().numpy()
-    cl32 = s32.cl.cpu().numpy()
-    cp32 = s32.cp.cpu().numpy()
+    w, xy, alpha, s64, s32 = setup(a.workload, a.batch, a.wave_limit)
+    noff, aoff = w.node_offsets(), w.alpha_offsets()
+    lu_f, solve_f, pairs = _work(w)
+    B = w.B
+    n_solves = int(aoff[-1])
+    use_graph = not a.no_graph
+
+    # FP64 and FP32 + refinement: breakdown (eager) and the timed step
+    k64 = eager(s64, xy, alpha, a.steps, a.warmup)
+    r64 = replay(s64, xy, alpha, a.steps, a.warmup, use_graph)
+    s64.step(xy, alpha)
+    torch.cuda.synchronize()
+    info64, cl64, cp64, gam64 = (s64.info.cpu().numpy(), s64.cl.cpu().numpy(), s64.cp.cpu().numpy(),
+                                 s64.gamma.cpu().numpy())
+    k32 = eager(s32, xy, alpha, a.steps, a.warmup)
+    r32 = replay(s32, xy, alpha, a.steps, a.warmup, use_graph)
+    s32.step(xy, alpha)
+    torch.cuda.synchronize()
+    info32, cl32, cp32, gam32 = (s32.info.cpu().numpy(), s32.cl.cpu().numpy(), s32.cp.cpu().numpy(),
+                                 s32.gamma.cpu().numpy())
     iters32 = s32.refine_iterations()
+    # FP32 factorisation alone (max_iter = 0 skips the refinement sweeps)
+    k32lu = eager(s32, xy, alpha, a.steps, a.warmup, max_iter=0)
+    s32.step(xy, alpha)   # leave the refined solution in place
+    torch.cuda.synchronize()
 
     v64 = n_solves / (r64["ms_per_step"] * 1e-3)
     v32 = n_solves / (r32["ms_per_step"] * 1e-3)
 
-    # adjoint (dCl/d nodes), timed on the FP64 factors
+    # adjoint on its own workload: 1024 sections at 6 degrees, FP64 forward
     adj = None
     if not a.no_adjoint:
-        try:
-            dcl = torch.ones(n_solves, dtype=torch.float64, device=dev)
-            dxy = torch.empty_like(xy)
-            s64.step(xy, alpha)
-            for _ in range(a.warmup):
-                s64.adjoint(xy, dcl, dxy)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(a.steps):
-                s64.adjoint(xy, dcl, dxy)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / a.steps
-            adj = {"gradients_per_s": B / (ms * 1e-3), "ms_per_step": ms,
-                   "fwd_plus_bwd_per_s": B / ((ms + r64["ms_per_step"]) * 1e-3)}
-        except P.PanelError as exc:
-            adj = {"error": str(exc)}
+        wa, xya, ala, sa, _ = setup("adjoint1024")
+        dcl = torch.ones(wa.B, dtype=torch.float64, device=dev)
+        dxy = torch.empty_like(xya)
+        fwd = replay(sa, xya, ala, a.steps, a.warmup, False)
+        sa.step(xya, ala)
+        for _ in range(a.warmup):
+            sa.adjoint(xya, dcl, out=dxy)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(a.steps):
+            sa.adjoint(xya, dcl, out=dxy)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / a.steps
+        adj = {"workload": f"adjoint1024: {wa.B} NACA sections, N=256, alpha=6 deg, FP64 factors",
+               "gradients_per_s": wa.B / (ms * 1e-3), "backward_ms": ms, "forward_ms": fwd["ms_per_step"],
+               "fwd_plus_bwd_per_s": wa.B / ((ms + fwd["ms_per_step"]) * 1e-3),
+               "bad_info": int(np.sum(sa.adj_info.cpu().numpy() != 0))}
+        del sa
 
-    # roofline of the dominant kernel (FP64 path): LU+solve on the matrix
-    # cores, or the transcendental-bound assembly on the vector ALUs.
-    lu_ms = r64["factor_solve_ms"]
-    asm_ms = r64["assemble_ms"]
-    lu_ach = (lu_f + solve_f) / (lu_ms * 1e-3)
-    asm_ach = pairs * ASM_FLOPS_PER_ENTRY / (asm_ms * 1e-3)
+    # roofline of every hot kernel of the step
+    def rate(flop, ms):
+        return flop / (ms * 1e-3)
+
+    lu64_ms = k64["factor_solve_ms"]
+    lu32_ms = k32lu["factor_solve_ms"]
+    ref_ms = max(k32["factor_solve_ms"] - lu32_ms, 1e-6)
+    n1 = w.n_panels.astype(np.float64) + 1
+    # refinement bytes: every sweep reads A64 (residual) and the FP32 factors
+    # (forward + back substitution) once
+    ref_bytes = float(np.sum(iters32.astype(np.float64) * 12.0 * n1 * n1))
     kern = {
-        "lu_solve_f64": {"bound": "mfma", "achieved": lu_ach / 1e12, "peak": PEAK["f64"] / 1e12,
-                         "unit": "TFLOP/s", "frac": lu_ach / PEAK["f64"], "ms": lu_ms,
-                         "work": "(2/3)n^3 + 2n^2K flops per airfoil"},
-        "assemble_f64": {"bound": "alu", "achieved": asm_ach / 1e12, "peak": PEAK["f64"] / 1e12,
-                         "unit": "TFLOP/s", "frac": asm_ach / PEAK["f64"], "ms": asm_ms,
+        "lu_solve_f64": {"bound": "mfma", "achieved": rate(lu_f + solve_f, lu64_ms) / 1e12,
+                         "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
+                         "frac": rate(lu_f + solve_f, lu64_ms) / PEAK["f64"], "ms": lu64_ms,
+                         "work": "(2/3)n1^3 + 2 n1^2 K flops per airfoil"},
+        "lu_solve_f32": {"bound": "mfma", "achieved": rate(lu_f + solve_f, lu32_ms) / 1e12,
+                         "peak": PEAK["f32"] / 1e12, "unit": "TFLOP/s",
+                         "frac": rate(lu_f + solve_f, lu32_ms) / PEAK["f32"], "ms": lu32_ms,
+                         "work": "(2/3)n1^3 + 2 n1^2 K flops per airfoil on the FP32 copy"},
+        "refine": {"bound": "hbm", "achieved": ref_bytes / (ref_ms * 1e-3) / 1e9, "peak": PEAK["hbm"] / 1e9,
+                   "unit": "GB/s", "frac": ref_bytes / (ref_ms * 1e-3) / PEAK["hbm"], "ms": ref_ms,
+                   "work": "per sweep 8 n1^2 B of A64 + 4 n1^2 B of FP32 factors per airfoil",
+                   "sweeps_mean": float(iters32.mean())},
+        "assemble_f64": {"bound": "alu", "achieved": rate(pairs * ASM_FLOPS_PER_ENTRY, k64["assemble_ms"]) / 1e12,
+                         "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
+                         "frac": rate(pairs * ASM_FLOPS_PER_ENTRY, k64["assemble_ms"]) / PEAK["f64"],
+                         "ms": k64["assemble_ms"],
                          "work": f"{ASM_FLOPS_PER_ENTRY:.0f} FP64 flops per influence entry"},
     }
-    dom = "lu_solve_f64" if lu_ms >= asm_ms else "assemble_f64"
-    roof = dict(kern[dom])
+    dom = "lu_solve_f64" if lu64_ms >= k64["assemble_ms"] else "assemble_f64"
     traffic = None
     if dom == "lu_solve_f64" and a.workload == "ga2048" and a.batch is None and a.wave_limit is None:
         import hashlib
         src = "lu_wave.hip"
         with open(os.path.join(os.path.dirname(P.__file__), "csrc", src), "rb") as f:
             traffic = LU_TRAFFIC.get((src, hashlib.sha256(f.read()).hexdigest()[:16]))
-    roof = {"kernel": dom, "bound": roof["bound"], "achieved": roof["achieved"], "peak": roof["peak"],
-            "unit": roof["unit"], "frac": roof["frac"], "traffic": traffic}
+    roof = {"kernel": dom, **{k: kern[dom][k] for k in ("bound", "achieved", "peak", "unit", "frac")},
+            "traffic": traffic}
+
+    # the other workloads' steps (parity-test cases; side figures only)
+    side = {}
+    if not a.no_side and a.batch is None:
+        for name in ("uneven4096", "large256"):
+            ws_, xs, als, t64, t32 = setup(name)
+            ns = int(ws_.alpha_offsets()[-1])
+            steps = max(3, a.steps // 4)
+            q64 = replay(t64, xs, als, steps, 1, use_graph)
+            q32 = replay(t32, xs, als, steps, 1, use_graph)
+            side[name] = {"airfoils": ws_.B, "angles": ns,
+                          "panels": [int(ws_.n_panels.min()), int(ws_.n_panels.max())],
+                          "fp64_ms_per_step": q64["ms_per_step"], "fp64_solves_per_s": ns / (q64["ms_per_step"] * 1e-3),
+                          "fp32_refine_ms_per_step": q32["ms_per_step"],
+                          "fp32_refine_solves_per_s": ns / (q32["ms_per_step"] * 1e-3)}
+            del t64, t32
+            torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC,
@@ -205,46 +297,71 @@ def main():
                                f"panels (cosine spacing, closed TE), one {int(w.n_panels.max()) + 1}-order "
                                f"system per airfoil, {n_solves} angle(s) total",
                    "airfoils": B, "panels": int(w.n_panels.max()), "angles": n_solves},
-        "fp64": dict(r64, solves_per_s=v64, bad_info=int(np.sum(info64 != 0))),
-        "fp32_refine": dict(r32, solves_per_s=v32, bad_info=int(np.sum(info32 != 0)),
+        "fp64": dict(r64, **k64, solves_per_s=v64, bad_info=int(np.sum(info64 != 0))),
+        "fp32_refine": dict(r32, **k32, solves_per_s=v32, bad_info=int(np.sum(info32 != 0)),
+                            lu_only_ms=lu32_ms, refine_ms=ref_ms,
                             refine_sweeps_max=int(iters32.max()), refine_sweeps_mean=float(iters32.mean())),
         "adjoint": adj,
         "roofline": roof,
         "roofline_kernels": kern,
+        "other_workloads": side,
     }
 
     if not a.no_cpu_baseline:
         import oracle
-        nthr = min(os.cpu_count() or 1, 16)
+        cpu = _cpu_info()
+        nthr = max(1, min(cpu["affinity"], CPU_SHARE))
         S = min(B, a.cpu_sample or B)
         idx = np.linspace(0, B - 1, S).astype(int)
         ws = w.subset(idx)
-        xy_o, noff_o = oracle.workload_nodes(ws)
-        w0 = ws.subset(np.arange(min(S, nthr)))          # untimed warm-up (pages, threads)
-        x0, n0 = oracle.workload_nodes(w0)
-        oracle.solve_batch(x0, n0, w0.alpha_flat(), w0.alpha_offsets(), nthreads=nthr)
-        t0 = time.perf_counter()
-        ref = oracle.solve_batch(xy_o, noff_o, ws.alpha_flat(), ws.alpha_offsets(), nthreads=nthr)
-        dt = time.perf_counter() - t0
+        # the oracle works on the GPU's own nodes (copied back)
+        xy_h = xy.cpu().numpy()
+        xy_o = np.concatenate([xy_h[2 * noff[b]:2 * noff[b + 1]] for b in idx])
+        noff_o = ws.node_offsets()
+        w0 = min(S, nthr)
+        oracle.solve_batch(xy_o[:2 * noff_o[w0]], noff_o[:w0 + 1], ws.alpha_flat()[:ws.alpha_offsets()[w0]],
+                           ws.alpha_offsets()[:w0 + 1], nthreads=nthr)   # untimed warm-up
+        times = []
+        ref = None
+        for _ in range(5):
+            t0 = time.perf_counter()
+            ref = oracle.solve_batch(xy_o, noff_o, ws.alpha_flat(), ws.alpha_offsets(), nthreads=nthr)
+            times.append(time.perf_counter() - t0)
+        dt = statistics.median(times)
+        # one core on a smaller sample
+        S1 = min(S, 128)
+        ws1 = ws.subset(np.arange(S1))
+        n1o = ws1.node_offsets()
+        times1 = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            r1 = oracle.solve_batch(xy_o[:2 * n1o[-1]], n1o, ws1.alpha_flat(), ws1.alpha_offsets(), nthreads=1)
+            times1.append(time.perf_counter() - t0)
+        dt1 = statistics.median(times1)
         # parity of the timed GPU results on the sampled airfoils
         aidx = np.concatenate([np.arange(aoff[i], aoff[i + 1]) for i in idx])
         so = np.concatenate([[0], np.cumsum((np.diff(noff) - 1) * np.diff(aoff))])
         cpidx = np.concatenate([np.arange(so[i], so[i + 1]) for i in idx])
 
-        def err(cl, cp):
+        def err(cl, cp, gam):
             ecl = np.max(np.abs(cl[aidx] - ref["cl"]) / np.maximum(1.0, np.abs(ref["cl"])))
             ecp = np.max(np.abs(cp[cpidx] - ref["cp"])) / max(1.0, np.max(np.abs(ref["cp"])))
-            return float(ecl), float(ecp)
+            eg = np.max(np.abs(gam[cpidx] - ref["gamma"])) / max(1.0, np.max(np.abs(ref["gamma"])))
+            return float(ecl), float(ecp), float(eg)
 
-        e64, p64 = err(cl64, cp64)
-        e32, p32 = err(cl32, cp32)
-        out["fp64"].update(cl_err=e64, cp_err=p64)
-        out["fp32_refine"].update(cl_err=e32, cp_err=p32)
+        e64, p64, g64 = err(cl64, cp64, gam64)
+        e32, p32, g32 = err(cl32, cp32, gam32)
+        out["fp64"].update(cl_err=e64, cp_err=p64, gamma_err=g64)
+        out["fp32_refine"].update(cl_err=e32, cp_err=p32, gamma_err=g32)
         out["cpu_baseline"] = {"value": int(ref["cl"].size) / dt, "unit": "solves/s",
                                "cores": int(ref["threads"]), "kind": "oracle",
-                               "sample": f"{S} of the {B} airfoils, full pipeline (nodes given; assembly, "
-                                         f"LU, solve, forces in plain C FP64, OpenMP over airfoils), "
-                                         f"{dt:.2f} s wall"}
+                               "sample": f"{S} of the {B} airfoils on the GPU's nodes, full pipeline (assembly, "
+                                         f"LU, solve, forces in plain C FP64, OpenMP over airfoils); median of 5 "
+                                         f"runs after a warm-up, {dt:.2f} s each",
+                               "one_core": {"value": int(r1["cl"].size) / dt1, "unit": "solves/s",
+                                            "sample": f"first {S1} of the sample, median of 5 runs, "
+                                                      f"{dt1:.2f} s each"},
+                               "host": cpu}
         out["cl_err_vs_oracle"] = {"fp64": e64, "fp32_refine": e32}
     print(json.dumps(out), flush=True)
 

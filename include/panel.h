@@ -22,8 +22,11 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Calls that take a stream only enqueue work on it: they never
  *    synchronise the device and never allocate device memory, so the
- *    sequence assemble -> factor_solve -> forces may be captured into a
- *    HIP graph.
+ *    sequence assemble -> factor_solve -> forces (and adjoint) may be
+ *    captured into a HIP graph.  The one exception is
+ *    panel_workspace_init, a host-to-device copy of the plan's metadata
+ *    that returns only once the copy is complete (so the plan may be
+ *    destroyed right after it); it is not meant for graph capture.
  *  - The caller owns all device memory, including the workspace, whose size
  *    panel_workspace_size reports.  The library keeps no device pointers
  *    between calls.  A plan owns host memory only.
@@ -37,6 +40,9 @@
  *      -1   non-finite node coordinate or zero-length panel; outputs NaN
  *      -2   mixed precision: refinement did not reach the tolerance within
  *           max_iter sweeps (the last iterate is returned)
+ *      -3   the workspace's airfoil order sends a system to a kernel that
+ *           cannot hold it (the plan changed after panel_workspace_init);
+ *           outputs NaN
  */
 #ifndef PANEL_H
 #define PANEL_H
@@ -95,7 +101,9 @@ void panel_plan_destroy(panel_plan *plan);
  *            Default 320.
  * Both kernels produce LAPACK getrf factors and pivots (largest |a|, lowest
  * row on ties).  Takes effect at the next panel_workspace_init (the airfoil
- * order lives in the workspace).  PANEL_EINVAL outside the range.         */
+ * order lives in the workspace): after a change, panel_factor_solve and
+ * panel_adjoint return PANEL_EINVAL until it has run.  PANEL_EINVAL
+ * outside the range.                                                       */
 panel_status panel_plan_set_wave_limit(panel_plan *plan, int32_t max_n1);
 
 /* Bytes of device workspace the plan needs (256-byte aligned base). */
@@ -152,18 +160,29 @@ panel_status panel_factor_solve(const panel_plan *plan, void *ws, double refine_
 panel_status panel_forces(const panel_plan *plan, const void *ws, double *gamma, double *cp,
                           double *cl, double *cl_p, void *stream);
 
-/* Reverse-mode sensitivity of the lift (cl above) to every node:
- *   dxy[2k + c] = sum over the airfoil's angles of dcl[.] * dCl/dP_k,c
+/* Reverse-mode sensitivity of the forces outputs to every node (the shape
+ * gradient of the Sec. 2 system, M(P) x = r(P, alpha)):
+ *   dxy[2k + c] = sum over the airfoil's angles a of
+ *                   dcl[a] dCl_a/dP_k,c + sum_i dcp[a, i] dCp_{a,i}/dP_k,c
  * for all N_b + 1 nodes of each airfoil (node 0 and node N are separate
- * variables).  Uses the factors left in the workspace by
- * panel_factor_solve (transposed solve; refined in FP64 for
+ * variables), with cl and cp as panel_forces defines them
+ * (dCp_i/dgamma_i = -2 gamma_i / vinf^2).  Uses the factors left in the
+ * workspace by panel_factor_solve (transposed solve; refined in FP64 for
  * PANEL_FP32_REFINE) and re-evaluates the assembly derivatives on the fly.
+ * Without dcp one pass serves every angle; with dcp the work is one pass
+ * per angle index.
  *   xy     the node array passed to panel_assemble
  *   dcl    alpha_offsets[B] cotangents of cl
+ *   dcp    cotangents of cp in panel_forces' layout, or NULL (all zero)
  *   dxy    2 * node_offsets[B] doubles, overwritten
- * Airfoils with info != 0 get NaN.                                         */
+ *   info   device int32[B] or NULL: 0, the factorisation's code for
+ *          airfoils that failed there, or -2 when (PANEL_FP32_REFINE) the
+ *          FP64 refinement of the transposed solve did not converge within
+ *          10 sweeps (the gradient is then less accurate)
+ * Airfoils whose factorisation failed get NaN.                            */
 panel_status panel_adjoint(const panel_plan *plan, const void *ws, const double *xy,
-                           const double *dcl, double *dxy, void *stream);
+                           const double *dcl, const double *dcp, double *dxy, int32_t *info,
+                           void *stream);
 
 /* NACA 4-digit sections (geometry helper for the GA population): cosine
  * spacing x = (1 + cos(pi s / (N/2)))/2, s = min(k, N - k), nodes 0..N/2 on

@@ -35,11 +35,11 @@ from ._binding import (  # noqa: F401
     panel_workspace_layout,
     panel_workspace_size,
 )
-from .solver import PanelSolver, panel_cl, naca_cl  # noqa: F401
+from .solver import PanelSolver, naca_cl, panel_cl, panel_cl_cp  # noqa: F401
 
 __all__ = [
     "PANEL_FP64", "PANEL_FP32_REFINE", "PANEL_NMAX", "PANEL_NMIN", "PANEL_KMAX",
-    "PanelError", "Plan", "PanelSolver", "panel_cl", "naca_cl",
+    "PanelError", "Plan", "PanelSolver", "panel_cl", "panel_cl_cp", "naca_cl",
     "panel_plan_create", "panel_plan_destroy", "panel_plan_set_wave_limit", "panel_workspace_size", "panel_workspace_init", "panel_workspace_layout",
     "panel_assemble", "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
     "panel_naca4_vjp", "panel_math_eval", "panel_status_str", "panel_last_error", "load_library", "lib_path",

@@ -46,7 +46,7 @@ def load_library():
     L.panel_assemble.argtypes = [vp, vp, vp, vp, f64, vp, vp]
     L.panel_factor_solve.argtypes = [vp, vp, f64, i32, vp, vp]
     L.panel_forces.argtypes = [vp, vp, vp, vp, vp, vp, vp]
-    L.panel_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.panel_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.panel_naca4.argtypes = [i32, vp, i32, vp, vp, vp]
     L.panel_naca4_vjp.argtypes = [i32, vp, i32, vp, vp, vp, vp]
     L.panel_math_eval.argtypes = [i32, vp, vp, vp, vp, vp]
@@ -201,11 +201,12 @@ def panel_forces(plan: Plan, ws, gamma, cp, cl, cl_p, stream=None):
                                        _ptr(cl, d, "cl"), _ptr(cl_p, d, "cl_p", True), _stream(stream)))
 
 
-def panel_adjoint(plan: Plan, ws, xy, dcl, dxy, stream=None):
+def panel_adjoint(plan: Plan, ws, xy, dcl, dcp, dxy, info=None, stream=None):
     import torch
     d = torch.float64
     _check(load_library().panel_adjoint(plan.handle, _ptr(ws, torch.uint8, "ws"), _ptr(xy, d, "xy"),
-                                        _ptr(dcl, d, "dcl"), _ptr(dxy, d, "dxy"), _stream(stream)))
+                                        _ptr(dcl, d, "dcl"), _ptr(dcp, d, "dcp", True), _ptr(dxy, d, "dxy"),
+                                        _ptr(info, torch.int32, "info", True), _stream(stream)))
 
 
 def panel_naca4(B, node_off, closed_te, mpt, xy, stream=None):

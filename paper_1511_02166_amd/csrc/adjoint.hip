@@ -135,14 +135,17 @@ __device__ void solve_transposed(const T *LU, int ld, int n, const int *perm, V 
 template <typename T>
 __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__restrict__ xy,
                                                       const double *__restrict__ dcl,
-                                                      double *__restrict__ dxy) {
+                                                      const double *__restrict__ dcp, int32_t ka,
+                                                      double *__restrict__ dxy, int32_t *__restrict__ info) {
     const int b = v.order[blockIdx.x];
     const AirfoilMeta mt = v.meta[b];
     const int N = mt.N, n1 = mt.n1, K = mt.K, ld = mt.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double *out = dxy + 2 * (size_t)mt.node_off;
+    if (ka >= K) return;   // per-angle pass past this airfoil's angles
     if (v.flag[b] != 0) {
         for (int k = tid; k < 2 * (N + 1); k += TPB) out[k] = __builtin_nan("");
+        if (info && tid == 0) info[b] = v.flag[b];
         return;
     }
     __shared__ double sx[PANEL_NMAX + 1], sy[PANEL_NMAX + 1];
@@ -161,15 +164,32 @@ __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__
     }
     const double vinf = v.hdr->vinf, chord = v.chord[b];
     const double *X = v.x + mt.x_off;
-    double S = 0.0, Cc = 0.0;
-    for (int k = 0; k < K; ++k) {
-        const double a = v.alpha[mt.alpha_off + k], d = dcl[mt.alpha_off + k];
-        S += d * sin(a);
-        Cc += d * cos(a);
+    // Cotangent seeds: all angles at once with cl cotangents only (ka < 0,
+    // one transposed solve; xbar = sum_k dcl_k x_k), or one angle with its
+    // cl and cp cotangents (ka >= 0; xbar = x_ka, the explicit length term
+    // scaled by dcl_ka).
+    double S = 0.0, Cc = 0.0, escale = 1.0;
+    if (ka < 0) {
+        for (int k = 0; k < K; ++k) {
+            const double a = v.alpha[mt.alpha_off + k], d = dcl[mt.alpha_off + k];
+            S += d * sin(a);
+            Cc += d * cos(a);
+        }
+    } else {
+        const double a = v.alpha[mt.alpha_off + ka];
+        S = sin(a);
+        Cc = cos(a);
+        escale = dcl[mt.alpha_off + ka];
     }
+    const double *cpbar = (ka >= 0 && dcp) ? dcp + mt.s_off + (size_t)ka * N : nullptr;
+    const double cpf = -2.0 / (vinf * vinf);
     for (int i = tid; i < n1; i += TPB) {
         double s = 0.0;
-        for (int k = 0; k < K; ++k) s += dcl[mt.alpha_off + k] * X[(size_t)k * n1 + i];
+        if (ka < 0) {
+            for (int k = 0; k < K; ++k) s += dcl[mt.alpha_off + k] * X[(size_t)k * n1 + i];
+        } else {
+            s = X[(size_t)ka * n1 + i];
+        }
         xbar[i] = s;
     }
     if (tid == 0) {
@@ -188,13 +208,15 @@ __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__
         double w = 0.0;
         if (i < N) {
             const double hx = sx[i + 1] - sx[i], hy = sy[i + 1] - sy[i];
-            w = wscale * sqrt(hx * hx + hy * hy);
+            w = escale * wscale * sqrt(hx * hx + hy * hy);
+            if (cpbar) w += cpbar[i] * cpf * xbar[i];
         }
         tmp[i] = w;
     }
     __syncthreads();
 
     const T *LU = factors<T>(v, mt);
+    bool conv = true;
     if constexpr (sizeof(T) == 8) {
         for (int i = tid; i < n1; i += TPB) lam[i] = tmp[i];
         __syncthreads();
@@ -216,6 +238,7 @@ __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__
         __syncthreads();
         const double floor_c = sqrt((double)n1) * 2.220446049250313e-16;
         double anrm = -1.0;
+        conv = false;
         for (int it = 0; it < 10; ++it) {
             // r = w - A^T lambda  (column i of A dotted with lambda)
             double rmax = 0.0, lmax = 0.0, cmax = 0.0;
@@ -244,7 +267,10 @@ __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__
             lmax = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
             if (anrm < 0.0) anrm = fmax(fmax(part[0], part[1]), fmax(part[2], part[3]));
             __syncthreads();
-            if (rmax <= floor_c * anrm * lmax) break;   // ||A^T||_inf = max column sum
+            if (rmax <= floor_c * anrm * lmax) {   // ||A^T||_inf = max column sum
+                conv = true;
+                break;
+            }
             for (int i = tid; i < n1; i += TPB) ylo[i] = (float)tmp[i];
             __syncthreads();
             solve_transposed<float, float>(LU, ld, n1, perm, ylo, tlo, sblk, partf);
@@ -265,8 +291,17 @@ __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__
             dmax = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
             ln = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
             __syncthreads();
-            if (dmax <= 1e-12 * ln) break;
+            if (dmax <= 1e-12 * ln) {
+                conv = true;
+                break;
+            }
         }
+    }
+    // info: 0, or -2 when the FP64 refinement of lambda ran out of sweeps
+    // (a later per-angle pass never clears an earlier failure)
+    if (info && tid == 0) {
+        if (!conv) info[b] = -2;
+        else if (ka <= 0) info[b] = 0;
     }
 
     // ---- pass 1: control points (dG/dm), one thread per row j -------------
@@ -355,7 +390,7 @@ __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__
             const int i = k - 1;
             const double hx = sx[i + 1] - sx[i], hy = sy[i + 1] - sy[i];
             const double iL = 1.0 / sqrt(hx * hx + hy * hy);
-            const double e = wscale * xbar[i];
+            const double e = escale * wscale * xbar[i];
             gx += e * hx * iL - gBx[i];
             gy += e * hy * iL - gBy[i];
             gx += 0.5 * (lam[i] * vinf * S - gmx[i]);
@@ -365,30 +400,44 @@ __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__
             const int i = k;
             const double hx = sx[i + 1] - sx[i], hy = sy[i + 1] - sy[i];
             const double iL = 1.0 / sqrt(hx * hx + hy * hy);
-            const double e = wscale * xbar[i];
+            const double e = escale * wscale * xbar[i];
             gx += -e * hx * iL - gAx[i];
             gy += -e * hy * iL - gAy[i];
             gx += 0.5 * (lam[i] * vinf * S - gmx[i]);
             gy += 0.5 * (-lam[i] * vinf * Cc - gmy[i]);
         }
-        out[2 * k] = gx;
-        out[2 * k + 1] = gy;
+        if (ka <= 0) {   // the first pass writes, later per-angle passes add
+            out[2 * k] = gx;
+            out[2 * k + 1] = gy;
+        } else {
+            out[2 * k] += gx;
+            out[2 * k + 1] += gy;
+        }
     }
 }
 
 }  // namespace
 
-hipError_t launch_adjoint(const WsView &v, int32_t B, int32_t n_block, int32_t mixed, const double *xy,
-                          const double *dcl, double *dxy, hipStream_t stream) {
-    if (n_block > 0) {
-        if (mixed)
-            adjoint_kernel<float><<<n_block, TPB, 0, stream>>>(v, xy, dcl, dxy);
-        else
-            adjoint_kernel<double><<<n_block, TPB, 0, stream>>>(v, xy, dcl, dxy);
-        const hipError_t e = hipGetLastError();
+hipError_t launch_adjoint(const WsView &v, int32_t B, int32_t n_block, int32_t max_k, int32_t mixed,
+                          const double *xy, const double *dcl, const double *dcp, double *dxy, int32_t *info,
+                          hipStream_t stream) {
+    // without cp cotangents one pass serves all angles; with them one pass
+    // per angle index (airfoils with fewer angles skip the later passes)
+    const int npass = dcp ? max_k : 1;
+    for (int p = 0; p < npass; ++p) {
+        const int ka = dcp ? p : -1;
+        if (n_block > 0) {
+            if (mixed)
+                adjoint_kernel<float><<<n_block, TPB, 0, stream>>>(v, xy, dcl, dcp, ka, dxy, info);
+            else
+                adjoint_kernel<double><<<n_block, TPB, 0, stream>>>(v, xy, dcl, dcp, ka, dxy, info);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        const hipError_t e = launch_adjoint_wave(v, n_block, B - n_block, mixed, xy, dcl, dcp, ka, dxy, info, stream);
         if (e != hipSuccess) return e;
     }
-    return launch_adjoint_wave(v, n_block, B - n_block, mixed, xy, dcl, dxy, stream);
+    return hipSuccess;
 }
 
 }  // namespace panel

@@ -128,14 +128,18 @@ template <typename T>
 __global__ __launch_bounds__(WL, 2) void adjoint_wave_kernel(WsView v, int32_t first,
                                                              const double *__restrict__ xy,
                                                              const double *__restrict__ dcl,
-                                                             double *__restrict__ dxy) {
+                                                             const double *__restrict__ dcp, int32_t ka,
+                                                             double *__restrict__ dxy,
+                                                             int32_t *__restrict__ info) {
     const int b = v.order[first + blockIdx.x];
     const AirfoilMeta mt = v.meta[b];
     const int N = mt.N, n1 = mt.n1, K = mt.K, ld = mt.ld;
     const int lane = threadIdx.x;
     double *out = dxy + 2 * (size_t)mt.node_off;
-    if (v.flag[b] != 0) {
+    if (ka >= K) return;   // per-angle pass past this airfoil's angles
+    if (v.flag[b] != 0 || n1 > NW) {
         for (int k = lane; k < 2 * (N + 1); k += WL) out[k] = __builtin_nan("");
+        if (info && lane == 0) info[b] = v.flag[b] != 0 ? v.flag[b] : -3;
         return;
     }
     __shared__ double xbar[NW], lam[NW], wv[NW], tmp[NW];
@@ -147,18 +151,40 @@ __global__ __launch_bounds__(WL, 2) void adjoint_wave_kernel(WsView v, int32_t f
     const PanelGeom *geo = v.geom + mt.panel_off;
     const double vinf = v.hdr->vinf, chord = v.chord[b];
     const double *X = v.x + mt.x_off;
-    double S = 0.0, Cc = 0.0;
-    for (int k = 0; k < K; ++k) {
-        const double a = v.alpha[mt.alpha_off + k], d = dcl[mt.alpha_off + k];
-        S += d * sin(a);
-        Cc += d * cos(a);
-    }
     const double wscale = -2.0 / (vinf * chord);
+    // Cotangent seeds.  All angles at once (ka < 0, cl cotangents only): the
+    // seed w = dCl/dx is the same for every angle, so one transposed solve
+    // serves them all with xbar = sum_k dcl_k x_k and the right-hand-side
+    // weights S, Cc summed likewise.  One angle (ka >= 0): the seed also
+    // carries dcp_i dCp_i/dgamma_i = -2 dcp_i gamma_i / vinf^2, so lambda is
+    // that angle's own; xbar = x_ka, and the explicit length term keeps the
+    // factor dcl_ka (escale).
+    double S = 0.0, Cc = 0.0, escale = 1.0;
+    if (ka < 0) {
+        for (int k = 0; k < K; ++k) {
+            const double a = v.alpha[mt.alpha_off + k], d = dcl[mt.alpha_off + k];
+            S += d * sin(a);
+            Cc += d * cos(a);
+        }
+    } else {
+        const double a = v.alpha[mt.alpha_off + ka];
+        S = sin(a);
+        Cc = cos(a);
+        escale = dcl[mt.alpha_off + ka];
+    }
+    const double *cpbar = (ka >= 0 && dcp) ? dcp + mt.s_off + (size_t)ka * N : nullptr;
+    const double cpf = -2.0 / (vinf * vinf);
     for (int i = lane; i < n1; i += WL) {
         double s = 0.0;
-        for (int k = 0; k < K; ++k) s += dcl[mt.alpha_off + k] * X[(size_t)k * n1 + i];
+        if (ka < 0) {
+            for (int k = 0; k < K; ++k) s += dcl[mt.alpha_off + k] * X[(size_t)k * n1 + i];
+        } else {
+            s = X[(size_t)ka * n1 + i];
+        }
         xbar[i] = s;
-        wv[i] = (i < N) ? wscale * geo[i].L : 0.0;
+        double w = (i < N) ? escale * wscale * geo[i].L : 0.0;
+        if (cpbar && i < N) w += cpbar[i] * cpf * s;
+        wv[i] = w;
         ox[i] = 0.0;
         oy[i] = 0.0;
     }
@@ -176,6 +202,7 @@ __global__ __launch_bounds__(WL, 2) void adjoint_wave_kernel(WsView v, int32_t f
 
     // ---- lambda = M^{-T} w -------------------------------------------------
     const T *LU = factors_of<T>(v, mt);
+    bool conv = true;
     if constexpr (sizeof(T) == 8) {
         for (int i = lane; i < n1; i += WL) tmp[i] = wv[i];
         __syncthreads();
@@ -189,6 +216,7 @@ __global__ __launch_bounds__(WL, 2) void adjoint_wave_kernel(WsView v, int32_t f
         wave_solve_t<float, float, double>(LU, ld, n1, perm, yf, lam);
         const double floor_c = sqrt((double)n1) * 2.220446049250313e-16;
         double anrm = -1.0;
+        conv = false;
         for (int it = 0; it < 10; ++it) {
             // r = w - A^T lambda: lane i walks column i of A
             double rmax = 0.0, lmax = 0.0, cmax = 0.0;
@@ -220,7 +248,10 @@ __global__ __launch_bounds__(WL, 2) void adjoint_wave_kernel(WsView v, int32_t f
             cmax = wave_max(cmax);
             if (anrm < 0.0) anrm = cmax;   // ||A^T||_inf = largest column sum
             __syncthreads();
-            if (rmax <= floor_c * anrm * lmax) break;
+            if (rmax <= floor_c * anrm * lmax) {
+                conv = true;
+                break;
+            }
             wave_solve_t<float, float, double>(LU, ld, n1, perm, yf, tmp);
             double dmax = 0.0, ln = 0.0;
             for (int i = lane; i < n1; i += WL) {
@@ -233,8 +264,17 @@ __global__ __launch_bounds__(WL, 2) void adjoint_wave_kernel(WsView v, int32_t f
             dmax = wave_max(dmax);
             ln = wave_max(ln);
             __syncthreads();
-            if (dmax <= 1e-12 * ln) break;
+            if (dmax <= 1e-12 * ln) {
+                conv = true;
+                break;
+            }
         }
+    }
+    // info: 0, or -2 when the FP64 refinement of lambda ran out of sweeps
+    // (a later per-angle pass never clears an earlier failure)
+    if (info && lane == 0) {
+        if (!conv) info[b] = -2;
+        else if (ka <= 0) info[b] = 0;
     }
 
     // ---- one pass over the panels ----------------------------------------
@@ -263,6 +303,7 @@ __global__ __launch_bounds__(WL, 2) void adjoint_wave_kernel(WsView v, int32_t f
         const PanelGeom g = geo[i];
         const double L = g.L, iL = 1.0 / L, tx = g.tx, ty = g.ty, nx = ty, ny = -tx;
         const double xb = xbar[i];
+        const double dGdL = -kInv2Pi * plog(0.5 * L);   // diagonal: dG_ii/dL
         double pbx = 0.0, pby = 0.0, psx = 0.0, psy = 0.0;
 #pragma unroll
         for (int q = 0; q < RM; ++q) {
@@ -281,9 +322,8 @@ __global__ __launch_bounds__(WL, 2) void adjoint_wave_kernel(WsView v, int32_t f
             const double bgx = kInv2Pi * iL * (itt * tx + inn * nx) + G * iL * tx;
             const double bgy = kInv2Pi * iL * (itt * ty + inn * ny) + G * iL * ty;
             // the diagonal (j == i): G_ii depends on the panel length only,
-            // dG/dB = dG/dL t, no control-point term; log(L/2) = l1 / 2 there
+            // dG/dB = dG/dL t, no control-point term
             const bool dg = jq[q] == i;
-            const double dGdL = -kInv2Pi * 0.5 * l1[q];
             const double lq = lj[q];
             pbx += lq * (dg ? dGdL * tx : bgx);
             pby += lq * (dg ? dGdL * ty : bgy);
@@ -323,7 +363,7 @@ __global__ __launch_bounds__(WL, 2) void adjoint_wave_kernel(WsView v, int32_t f
             const int j = jq[q];
             if (j >= 0) {
                 const PanelGeom g = geo[j];
-                const double e = wscale * xbar[j];
+                const double e = escale * wscale * xbar[j];
                 const double gmx = -kInv2Pi * lj[q] * ax[q], gmy = -kInv2Pi * lj[q] * ay[q];
                 const double cx = 0.5 * (lj[q] * vinf * S - gmx), cy = 0.5 * (-lj[q] * vinf * Cc - gmy);
                 if (half == 0) {   // node j: start of panel j
@@ -337,21 +377,28 @@ __global__ __launch_bounds__(WL, 2) void adjoint_wave_kernel(WsView v, int32_t f
         }
         __syncthreads();
     }
+    // the first pass writes, later per-angle passes add their share
     for (int k = lane; k <= N; k += WL) {
-        out[2 * k] = ox[k];
-        out[2 * k + 1] = oy[k];
+        if (ka <= 0) {
+            out[2 * k] = ox[k];
+            out[2 * k + 1] = oy[k];
+        } else {
+            out[2 * k] += ox[k];
+            out[2 * k + 1] += oy[k];
+        }
     }
 }
 
 }  // namespace
 
 hipError_t launch_adjoint_wave(const WsView &v, int32_t first, int32_t count, int32_t mixed, const double *xy,
-                               const double *dcl, double *dxy, hipStream_t stream) {
+                               const double *dcl, const double *dcp, int32_t ka, double *dxy, int32_t *info,
+                               hipStream_t stream) {
     if (count <= 0) return hipSuccess;
     if (mixed)
-        adjoint_wave_kernel<float><<<count, WL, 0, stream>>>(v, first, xy, dcl, dxy);
+        adjoint_wave_kernel<float><<<count, WL, 0, stream>>>(v, first, xy, dcl, dcp, ka, dxy, info);
     else
-        adjoint_wave_kernel<double><<<count, WL, 0, stream>>>(v, first, xy, dcl, dxy);
+        adjoint_wave_kernel<double><<<count, WL, 0, stream>>>(v, first, xy, dcl, dcp, ka, dxy, info);
     return hipGetLastError();
 }
 

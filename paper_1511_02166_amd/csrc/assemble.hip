@@ -13,9 +13,11 @@
 // which is the closed form of the integral with the difference of the two
 // arctangents folded into one (the angle subtended by the panel) and the
 // logarithm of |m_j - P_{i+1}|^2 shared between panels i and i+1.  The
-// self-influence is the midpoint limit (L/2pi)(1 - log(L/2)), evaluated with
-// the shared logarithm (|m_j - P_j| = L/2).  log and atan2 are the library's
-// own (fastmath.hpp).
+// self-influence is the midpoint limit (L/2pi)(1 - log(L/2)) as a function of
+// the panel length alone (the shared logarithm of |m_j - P_j|^2 would carry
+// the rounding of the stored midpoint, which on the shortest panels moves it
+// by up to ~1e-12 relative).  log and atan2 are the library's own
+// (fastmath.hpp).
 //
 // One workgroup covers COLS consecutive columns of one airfoil's augmented
 // matrix [M | rhs] (column-major, leading dimension ld, rows n1..ld-1
@@ -92,17 +94,18 @@ __global__ __launch_bounds__(256) void assemble_kernel(WsView v, const double *_
 
     if (c0 + COLS <= N) {
         // Interior block: all COLS columns are panel columns.  Branch-free;
-        // the diagonal entry reuses the shared logarithm, since
-        // log(L/2) = log|m_j - P_j|^2 / 2 on the diagonal.
-        __shared__ double shx[COLS], shy[COLS], sL2[COLS], siL[COLS];
+        // the diagonal value of each column is formed once here.
+        __shared__ double shx[COLS], shy[COLS], sL2[COLS], siL[COLS], sdg[COLS];
         if (threadIdx.x < COLS) {
             const int c = c0 + threadIdx.x;
             const double hx = sx[c + 1] - sx[c], hy = sy[c + 1] - sy[c];
             const double L2 = hx * hx + hy * hy;
+            const double L = sqrt(L2);
             shx[threadIdx.x] = hx;
             shy[threadIdx.x] = hy;
             sL2[threadIdx.x] = L2;
-            siL[threadIdx.x] = 1.0 / sqrt(L2);
+            siL[threadIdx.x] = 1.0 / L;
+            sdg[threadIdx.x] = kInv2Pi * L * (1.0 - plog(0.5 * L));
         }
         __syncthreads();
         for (int j = threadIdx.x; j < ld; j += blockDim.x) {
@@ -124,8 +127,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(WsView v, const double *_
                     const double dd = d1x * d2x + d1y * d2y;
                     const double ang = patan2(cr, dd);
                     const double gen = -kInv4Pi * iL * (dot1 * l1 - (dot1 - L2) * l2 - 2.0 * L2 + 2.0 * cr * ang);
-                    const double diag = kInv2Pi * L2 * iL * (1.0 - 0.5 * l1);
-                    const double g = (c == j) ? diag : gen;
+                    const double g = (c == j) ? sdg[cc] : gen;
                     Aj[(size_t)cc * ld] = g;
                     if (MIXED) A32j[(size_t)cc * ld] = (float)g;
                     d1x = d2x;
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(WsView v, const double *_
                     const double L2 = hx * hx + hy * hy;
                     const double L = sqrt(L2);
                     if (c == j) {
-                        g = L * kInv2Pi * (1.0 - 0.5 * l1);
+                        g = L * kInv2Pi * (1.0 - plog(0.5 * L));
                     } else {
                         const double dot1 = d1x * hx + d1y * hy;
                         const double cr = d1x * d2y - d1y * d2x;

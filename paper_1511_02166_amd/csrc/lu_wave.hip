@@ -585,8 +585,15 @@ __global__ __launch_bounds__(WL, 2) void lu_wave_kernel(WsView v, int32_t first,
     const int lane = threadIdx.x;
     double *X = v.x + mt.x_off;
 
-    if (v.flag[b] != 0) {   // screened out by the assembly
-        if (lane == 0) info_out[b] = -1;
+    if (v.flag[b] != 0 || n > WL * PANEL_WAVE_RMAX) {
+        // screened out by the assembly (-1), or a system too large for one
+        // wavefront (-3: the workspace's airfoil order does not match the
+        // plan it is used with)
+        const int code = v.flag[b] != 0 ? -1 : -3;
+        if (lane == 0) {
+            info_out[b] = code;
+            v.flag[b] = code;
+        }
         for (int i = lane; i < n * mt.K; i += WL) X[i] = __builtin_nan("");
         return;
     }

@@ -22,6 +22,9 @@ struct panel_plan {
     int32_t wave_max_n1 = PANEL_WAVE_MAX_N1;  // largest order given to the one-wavefront LU
     int32_t n_block = 0;       // airfoils factored by the workgroup LU (first in order)
     int32_t max_n1_block = 0;  // their largest order
+    // set when the wave limit changed after the last panel_workspace_init:
+    // the airfoil order in the workspace no longer matches n_block
+    mutable bool order_stale = false;
     std::vector<int32_t> node_off, alpha_off;
     std::vector<double> cost;  // LPT key: (2/3) n1^3 + 2 n1^2 K
     std::vector<char> blob;  // header | meta | order, copied by workspace_init
@@ -212,8 +215,11 @@ panel_status panel_plan_set_wave_limit(panel_plan *plan, int32_t max_n1) {
         std::snprintf(buf, sizeof buf, "wave limit must be in 0..%d", PANEL_WAVE_MAX_N1);
         return fail(PANEL_EINVAL, buf);
     }
-    plan->wave_max_n1 = max_n1;
-    build_order(plan);
+    if (max_n1 != plan->wave_max_n1) {
+        plan->wave_max_n1 = max_n1;
+        build_order(plan);
+        plan->order_stale = true;
+    }
     return ok();
 }
 
@@ -249,6 +255,7 @@ panel_status panel_workspace_init(const panel_plan *plan, void *ws, void *stream
     // The source is pageable host memory owned by the plan; make the copy
     // complete before returning so the plan may be destroyed at any time.
     e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) plan->order_stale = false;
     return check_hip(e, "workspace metadata copy");
 }
 
@@ -275,6 +282,8 @@ panel_status panel_factor_solve(const panel_plan *plan, void *ws, double refine_
             return fail(PANEL_EINVAL, "refine_tol must be finite and > 0");
         if (max_iter < 0 || max_iter > 100) return fail(PANEL_EINVAL, "max_iter must be in 0..100");
     }
+    if (plan->order_stale)
+        return fail(PANEL_EINVAL, "wave limit changed: call panel_workspace_init before factoring");
     WsView v = ws_view(ws, plan->layout);
     hipError_t e = launch_factor_solve(v, plan->B, plan->n_block, plan->max_n1_block, mixed, refine_tol,
                                        max_iter, info, static_cast<hipStream_t>(stream));
@@ -293,13 +302,18 @@ panel_status panel_forces(const panel_plan *plan, const void *ws, double *gamma,
 }
 
 panel_status panel_adjoint(const panel_plan *plan, const void *ws, const double *xy,
-                           const double *dcl, double *dxy, void *stream) {
+                           const double *dcl, const double *dcp, double *dxy, int32_t *info,
+                           void *stream) {
     if (!plan || !ws || !xy || !dcl || !dxy) return fail(PANEL_EINVAL, "NULL argument");
-    if (!aligned8(xy) || !aligned8(dcl) || !aligned8(dxy))
-        return fail(PANEL_EINVAL, "arrays must be 8-byte aligned");
+    if (!aligned8(xy) || !aligned8(dcl) || !aligned8(dxy) || (dcp && !aligned8(dcp)) ||
+        (reinterpret_cast<uintptr_t>(info) & 3u))
+        return fail(PANEL_EINVAL, "arrays must be aligned (8 bytes; info 4 bytes)");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(PANEL_EINVAL, "workspace must be 256-byte aligned");
+    if (plan->order_stale)
+        return fail(PANEL_EINVAL, "wave limit changed: call panel_workspace_init (and refactor) first");
     WsView v = ws_view(const_cast<void *>(ws), plan->layout);
-    hipError_t e = launch_adjoint(v, plan->B, plan->n_block, plan->precision == PANEL_FP32_REFINE, xy,
-                                  dcl, dxy, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_adjoint(v, plan->B, plan->n_block, plan->max_k, plan->precision == PANEL_FP32_REFINE,
+                                  xy, dcl, dcp, dxy, info, static_cast<hipStream_t>(stream));
     return check_hip(e, "adjoint launch");
 }
 

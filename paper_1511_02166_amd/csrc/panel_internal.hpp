@@ -105,9 +105,13 @@ hipError_t launch_forces(const WsView &v, int32_t B, int32_t max_k, double *gamm
                          double *cl, double *cl_p, hipStream_t stream);
 hipError_t launch_math_eval(int32_t n, const double *x, const double *y, double *lg, double *at,
                             hipStream_t stream);
-hipError_t launch_adjoint(const WsView &v, int32_t B, int32_t n_block, int32_t mixed,
-                          const double *xy, const double *dcl, double *dxy, hipStream_t stream);
+// ka < 0: one pass with cl cotangents for all angles; ka >= 0: angle ka
+// only, with its cl and (dcp non-NULL) cp cotangents, added to dxy for ka > 0.
+hipError_t launch_adjoint(const WsView &v, int32_t B, int32_t n_block, int32_t max_k, int32_t mixed,
+                          const double *xy, const double *dcl, const double *dcp, double *dxy, int32_t *info,
+                          hipStream_t stream);
 hipError_t launch_adjoint_wave(const WsView &v, int32_t first, int32_t count, int32_t mixed, const double *xy,
-                               const double *dcl, double *dxy, hipStream_t stream);
+                               const double *dcl, const double *dcp, int32_t ka, double *dxy, int32_t *info,
+                               hipStream_t stream);
 
 }  // namespace panel

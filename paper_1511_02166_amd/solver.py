@@ -42,8 +42,12 @@ class PanelSolver:
         self.cl_p = torch.empty(p.n_alpha, **f64)
         self.gamma = torch.empty(p.n_out, **f64)
         self.cp = torch.empty(p.n_out, **f64)
+        self.adj_info = torch.zeros(p.B, dtype=torch.int32, device=self.device)
         self.node_off_dev = torch.as_tensor(p.node_offsets, dtype=torch.int32, device=self.device)
         B.panel_workspace_init(p, self.ws)
+        # counts forward solves: the adjoint uses whatever factors the
+        # workspace holds, so autograd checks that they are still its own
+        self.steps = 0
 
     @property
     def B(self) -> int:
@@ -101,15 +105,18 @@ class PanelSolver:
         self.assemble(xy, alpha, chord, vinf)
         self.factor_solve(refine_tol, max_iter)
         self.forces(fields)
+        self.steps += 1
 
     def solve(self, xy, alpha, chord=None, vinf=1.0, refine_tol=1e-10, max_iter=10):
         self.step(xy, alpha, chord, vinf, refine_tol, max_iter)
         return dict(gamma=self.gamma, cp=self.cp, cl=self.cl, cl_p=self.cl_p, info=self.info)
 
-    def adjoint(self, xy, dcl, out=None):
+    def adjoint(self, xy, dcl, dcp=None, out=None):
+        """d/d(nodes) of sum(dcl * cl) + sum(dcp * cp) for the last step's
+        factors (per-airfoil status in ``adj_info``)."""
         dxy = out if out is not None else torch.empty(2 * self.plan.n_nodes, dtype=torch.float64,
                                                       device=self.device)
-        B.panel_adjoint(self.plan, self.ws, xy, dcl, dxy)
+        B.panel_adjoint(self.plan, self.ws, xy, dcl, dcp, dxy, self.adj_info)
         return dxy
 
     def naca4_vjp(self, mpt, dxy, closed_te=True):
@@ -143,25 +150,46 @@ class PanelSolver:
 
 
 class _ClFunction(torch.autograd.Function):
-    """Cl(xy) with the hand-written adjoint kernel as its backward."""
+    """(Cl, Cp)(xy) with the hand-written adjoint kernels as the backward."""
 
     @staticmethod
     def forward(ctx, xy, alpha, solver: PanelSolver, chord, vinf):
-        solver.step(xy, alpha, chord, vinf, fields=False)
+        solver.step(xy, alpha, chord, vinf, fields=True)
         ctx.solver = solver
+        ctx.step_id = solver.steps
+        ctx.args = (alpha, chord, vinf)
         ctx.save_for_backward(xy)
-        return solver.cl.clone()
+        ctx.set_materialize_grads(False)
+        return solver.cl.clone(), solver.cp.clone()
 
     @staticmethod
-    def backward(ctx, dcl):
+    def backward(ctx, dcl, dcp):
         (xy,) = ctx.saved_tensors
-        dxy = ctx.solver.adjoint(xy, dcl.contiguous())
+        s = ctx.solver
+        if dcl is None and dcp is None:
+            return None, None, None, None, None
+        if s.steps != ctx.step_id:
+            # the solver has solved another batch since this forward: redo
+            # this one so the adjoint sees its own factors (this overwrites
+            # the solver's output buffers with this forward's values)
+            alpha, chord, vinf = ctx.args
+            s.step(xy, alpha, chord, vinf, fields=False)
+            ctx.step_id = s.steps
+        if dcl is None:
+            dcl = torch.zeros(s.plan.n_alpha, dtype=torch.float64, device=s.device)
+        dxy = s.adjoint(xy, dcl.contiguous(), None if dcp is None else dcp.contiguous())
         return dxy, None, None, None, None
+
+
+def panel_cl_cp(xy, alpha, solver: PanelSolver, chord=None, vinf=1.0):
+    """Lift and pressure coefficients of a batch, (cl, cp), differentiable
+    with respect to the nodes."""
+    return _ClFunction.apply(xy, alpha, solver, chord, vinf)
 
 
 def panel_cl(xy, alpha, solver: PanelSolver, chord=None, vinf=1.0):
     """Lift coefficients of a batch, differentiable with respect to the nodes."""
-    return _ClFunction.apply(xy, alpha, solver, chord, vinf)
+    return _ClFunction.apply(xy, alpha, solver, chord, vinf)[0]
 
 
 class _NacaFunction(torch.autograd.Function):

@@ -80,6 +80,22 @@ def test_plan_validation(lib):
     lib.panel_plan_destroy(h)
 
 
+def test_changed_wave_limit_requires_workspace_init(lib):
+    # The airfoil order lives in the workspace: after the limit changes, the
+    # factorisation and the adjoint refuse to run (before any HIP call) until
+    # panel_workspace_init has copied the new order.
+    import paper_1511_02166_amd as P
+    EINVAL = P._binding.PANEL_EINVAL
+    st, h = _plan(lib, [0, 129, 500], [0, 1, 2])
+    fake = C.c_void_p(0x100000)
+    assert lib.panel_plan_set_wave_limit(h, 320) == 0           # unchanged: stays valid
+    assert lib.panel_plan_set_wave_limit(h, 0) == 0
+    assert lib.panel_factor_solve(h, fake, C.c_double(1e-10), 10, fake, None) == EINVAL
+    assert b"panel_workspace_init" in lib.panel_last_error()
+    assert lib.panel_adjoint(h, fake, fake, fake, None, fake, None, None) == EINVAL
+    lib.panel_plan_destroy(h)
+
+
 def test_entry_points_reject_bad_arguments_before_hip(lib):
     import paper_1511_02166_amd as P
     EINVAL = P._binding.PANEL_EINVAL
@@ -96,7 +112,9 @@ def test_entry_points_reject_bad_arguments_before_hip(lib):
     assert lib.panel_factor_solve(h, fake, C.c_double(1e-10), 101, fake, None) == EINVAL
     assert lib.panel_factor_solve(h, fake, C.c_double(1e-10), 3, None, None) == EINVAL
     assert lib.panel_forces(h, fake, None, None, None, None, None) == EINVAL
-    assert lib.panel_adjoint(h, fake, fake, None, fake, None) == EINVAL
+    assert lib.panel_adjoint(h, fake, fake, None, None, fake, None, None) == EINVAL
+    assert lib.panel_adjoint(h, fake, fake, fake, odd, fake, None, None) == EINVAL
+    assert lib.panel_adjoint(h, fake, fake, fake, None, fake, C.c_void_p(0x100002), None) == EINVAL
     assert lib.panel_naca4(0, fake, 1, fake, fake, None) == EINVAL
     assert lib.panel_naca4_vjp(2, fake, 1, fake, None, fake, None) == EINVAL
     lib.panel_plan_destroy(h)

@@ -71,7 +71,7 @@ def test_adjoint_matches_oracle_identical_nodes(prec, tol, wave_limit):
 
 
 def test_adjoint_naca_sample():
-    # N = 256, alpha = 6 deg; each side builds its own NACA nodes.
+    # N = 256, alpha = 6 deg; the GPU's NACA nodes, copied back, feed the oracle.
     import torch
     import paper_1511_02166_amd as P
     _say("adjoint vs oracle, adjoint1024[:6] NACA N=256")
@@ -81,8 +81,7 @@ def test_adjoint_naca_sample():
     al = torch.as_tensor(w.alpha_flat(), device="cuda")
     s.step(xy, al)
     g = s.adjoint(xy, torch.ones(w.B, dtype=torch.float64, device="cuda")).cpu().numpy()
-    xo, noff = oracle.workload_nodes(w)
-    ref = _oracle_grad(xo, noff, w.alpha, [np.ones(1)] * w.B)
+    ref = _oracle_grad(xy.cpu().numpy(), w.node_offsets(), w.alpha, [np.ones(1)] * w.B)
     e = _rel(g, ref)
     _say(f"  rel err {e:.3e}")
     assert e < 1e-9
@@ -215,3 +214,88 @@ def test_adjoint_kernels_agree(prec):
     e = _rel(gw, gb)
     _say(f"  rel diff {e:.3e}")
     assert e < (1e-9 if prec == 0 else 1e-8)
+
+
+def _oracle_force_grad(xy_flat, noff, alphas, dcl, dcp_flat, so, vinf=1.0, chords=None):
+    out = np.zeros_like(xy_flat)
+    for b in range(len(noff) - 1):
+        xyb = xy_flat[2 * noff[b]:2 * noff[b + 1]].reshape(-1, 2)
+        N = xyb.shape[0] - 1
+        c = 1.0 if chords is None else chords[b]
+        g = sum(oracle.force_gradient(xyb, alphas[b][k], dcl[b][k],
+                                      dcp_flat[so[b] + k * N:so[b] + (k + 1) * N], vinf, c)
+                for k in range(len(alphas[b])))
+        out[2 * noff[b]:2 * noff[b + 1]] = g.reshape(-1)
+    return out
+
+
+@pytest.mark.parametrize("prec,tol,wave_limit", [(0, 1e-9, None), (1, 1e-8, None), (0, 1e-9, 0), (1, 1e-8, 0)])
+def test_adjoint_with_cp_cotangents(prec, tol, wave_limit):
+    # dxy of sum dcl Cl + sum dcp Cp (one adjoint pass per angle index)
+    # against the oracle's tangent-linear gradient with the same weights,
+    # on uneven N and K, chords and vinf != 1.
+    import torch
+    import paper_1511_02166_amd as P
+    _say(f"adjoint with Cp cotangents, precision={prec}, wave_limit={wave_limit}")
+    xy_flat, noff = synth.joukowski_batch(27, 4, [40, 64, 96, 130])
+    rng = np.random.default_rng(27)
+    Ks = [1, 3, 2, 1]
+    alphas = [rng.uniform(-4, 10, k) * DEG for k in Ks]
+    aoff = np.concatenate([[0], np.cumsum(Ks)]).astype(np.int32)
+    Ns = np.diff(noff) - 1
+    so = np.concatenate([[0], np.cumsum(Ns * np.array(Ks))])
+    dcl = [rng.standard_normal(k) for k in Ks]
+    dcp = rng.standard_normal(int(so[-1]))
+    chords = rng.uniform(0.5, 1.5, 4)
+    vinf = 1.3
+    s = P.PanelSolver(noff, aoff, prec, wave_limit=wave_limit)
+    xy = torch.as_tensor(xy_flat, device="cuda")
+    s.step(xy, torch.as_tensor(np.concatenate(alphas), device="cuda"),
+           chord=torch.as_tensor(chords, device="cuda"), vinf=vinf)
+    g = s.adjoint(xy, torch.as_tensor(np.concatenate(dcl), device="cuda"),
+                  torch.as_tensor(dcp, device="cuda")).cpu().numpy()
+    info = s.adj_info.cpu().numpy()
+    ref = _oracle_force_grad(xy_flat, noff, alphas, dcl, dcp, so, vinf, chords)
+    e = _rel(g, ref)
+    _say(f"  rel err {e:.3e}, info {list(info)}")
+    assert np.all(info == 0)
+    assert e < tol
+
+
+def test_autograd_cl_cp_and_stale_forward():
+    # (cl, cp) from the autograd Function; the backward of an earlier forward
+    # after the solver has solved another batch must still give that
+    # forward's gradient.
+    import torch
+    import paper_1511_02166_amd as P
+    _say("autograd (cl, cp), stale forward")
+    xy_flat, noff = synth.joukowski_batch(25, 2, [48, 80])
+    aoff = np.array([0, 1, 3], dtype=np.int32)
+    al_np = np.array([2.0, 5.0, -1.0]) * DEG
+    s = _solver(noff, aoff)
+    al = torch.as_tensor(al_np, device="cuda")
+    xy = torch.as_tensor(xy_flat, device="cuda").requires_grad_(True)
+    cl, cp = P.panel_cl_cp(xy, al, s)
+    rng = np.random.default_rng(2)
+    wcl = torch.as_tensor(rng.standard_normal(3), device="cuda")
+    wcp = torch.as_tensor(rng.standard_normal(cp.numel()), device="cuda")
+    loss = (cl * wcl).sum() + (cp * wcp).sum()
+    # another forward on different nodes before the backward
+    other = torch.as_tensor(xy_flat * 1.1 + 0.05, device="cuda")
+    P.panel_cl(other, al, s)
+    loss.backward()
+    Ns = np.diff(noff) - 1
+    Ks = np.diff(aoff)
+    so = np.concatenate([[0], np.cumsum(Ns * Ks)])
+    alphas = [al_np[:1], al_np[1:]]
+    wcl_np = wcl.cpu().numpy()
+    ref = _oracle_force_grad(xy_flat, noff, alphas, [wcl_np[:1], wcl_np[1:]], wcp.cpu().numpy(), so)
+    e = _rel(xy.grad.cpu().numpy(), ref)
+    _say(f"  rel err {e:.3e}")
+    assert e < 1e-9
+    # cp only (cl unused): the cl cotangent is taken as zero
+    xy2 = torch.as_tensor(xy_flat, device="cuda").requires_grad_(True)
+    _, cp2 = P.panel_cl_cp(xy2, al, s)
+    (cp2 * wcp).sum().backward()
+    ref2 = _oracle_force_grad(xy_flat, noff, alphas, [np.zeros(1), np.zeros(2)], wcp.cpu().numpy(), so)
+    assert _rel(xy2.grad.cpu().numpy(), ref2) < 1e-9

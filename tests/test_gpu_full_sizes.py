@@ -7,8 +7,11 @@ batch is checked through properties that hold at any size: the Kutta row
 discrete translation and scaling invariants of Cl.
 
 Tolerances follow the parity tests: 1e-10 (FP64) and 1e-8 (FP32 factors with
-FP64 refinement) on e_Cl and e_Cp, raised to 2e-17 kappa where the sampled
-system's condition number kappa puts the FP64 floor above them (N = 1024).
+FP64 refinement) on e_gamma, e_Cp, e_Cl and e_Cl_p, or FLOOR_FACTOR times the
+floor measured on the sampled system from the oracle alone where that is
+larger (at N = 1024 two correct FP64 solutions already differ by ~1e-10 in
+gamma); the floor is logged beside each error.  The oracle always works on
+the node array the GPU used (copied back from the device).
 """
 import sys
 
@@ -17,6 +20,7 @@ import pytest
 
 import oracle
 import synth
+from _floor import FLOOR_FACTOR, measured_floor
 
 pytestmark = pytest.mark.gpu
 
@@ -74,38 +78,40 @@ def _check_batch_properties(w, got, precision):
     assert d < 2e-2
 
 
-def _check_sample(w, got, idx, precision):
+def _check_sample(w, got, idx, precision, xy):
+    """Sampled airfoils against the oracle on the GPU's own nodes."""
+    xy = xy.cpu().numpy() if hasattr(xy, "cpu") else np.asarray(xy)
     Ns, Ks, aoff, so = _slices(w)
+    noff = w.node_offsets()
     ws = w.subset(idx)
-    xo, noff_o = oracle.workload_nodes(ws)
+    noff_o = ws.node_offsets()
+    xo = np.concatenate([xy[2 * noff[b]:2 * noff[b + 1]] for b in idx])
     ref = oracle.solve_batch(xo, noff_o, ws.alpha_flat(), ws.alpha_offsets())
     _, Ks_o, aoff_o, so_o = _slices(ws)
     for r, b in enumerate(idx):
-        cl = got["cl"][aoff[b]:aoff[b + 1]]
-        clp = got["cl_p"][aoff[b]:aoff[b + 1]]
-        cp = got["cp"][so[b]:so[b + 1]]
-        rcl = ref["cl"][aoff_o[r]:aoff_o[r + 1]]
-        rclp = ref["cl_p"][aoff_o[r]:aoff_o[r + 1]]
-        rcp = ref["cp"][so_o[r]:so_o[r + 1]]
-        tol = TOL[precision]
-        if Ns[b] > 512:
-            xb = xo[2 * noff_o[r]:2 * noff_o[r + 1]]
-            kappa = np.linalg.cond(oracle.assemble(xb, [0.0])[0])
-            tol = max(tol, 2e-17 * kappa)
-        e_cl = np.max(np.abs(cl - rcl) / np.maximum(1.0, np.abs(rcl)))
-        e_clp = np.max(np.abs(clp - rclp) / np.maximum(1.0, np.abs(rclp)))
-        e_cp = np.max(np.abs(cp - rcp)) / max(1.0, np.max(np.abs(rcp)))
-        _say(f"  airfoil {b} N={Ns[b]} K={Ks[b]}: e_Cl {e_cl:.1e} e_Clp {e_clp:.1e} e_Cp {e_cp:.1e} (tol {tol:.0e})")
-        assert e_cl < tol and e_clp < tol and e_cp < tol, (b, e_cl, e_clp, e_cp)
+        g = dict(cl=got["cl"][aoff[b]:aoff[b + 1]], cl_p=got["cl_p"][aoff[b]:aoff[b + 1]],
+                 cp=got["cp"][so[b]:so[b + 1]], gamma=got["gamma"][so[b]:so[b + 1]])
+        o = dict(cl=ref["cl"][aoff_o[r]:aoff_o[r + 1]], cl_p=ref["cl_p"][aoff_o[r]:aoff_o[r + 1]],
+                 cp=ref["cp"][so_o[r]:so_o[r + 1]], gamma=ref["gamma"][so_o[r]:so_o[r + 1]])
+        e = dict(cl=np.max(np.abs(g["cl"] - o["cl"]) / np.maximum(1.0, np.abs(o["cl"]))),
+                 cl_p=np.max(np.abs(g["cl_p"] - o["cl_p"]) / np.maximum(1.0, np.abs(o["cl_p"]))),
+                 cp=np.max(np.abs(g["cp"] - o["cp"])) / max(1.0, np.max(np.abs(o["cp"]))),
+                 gamma=np.max(np.abs(g["gamma"] - o["gamma"])) / max(1.0, np.max(np.abs(o["gamma"]))))
+        fl = measured_floor(xo[2 * noff_o[r]:2 * noff_o[r + 1]], w.alpha[b])
+        msg = " ".join(f"{q} {e[q]:.1e}/{fl[q]:.0e}" for q in ("cl", "cl_p", "cp", "gamma"))
+        _say(f"  airfoil {b} N={Ns[b]} K={Ks[b]}: error/floor {msg}")
+        for q in ("cl", "cl_p", "cp", "gamma"):
+            tol = max(TOL[precision], FLOOR_FACTOR * fl[q])
+            assert e[q] < tol, (b, q, e[q], fl[q])
 
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_ga_batch_2048_n256(precision):
     w = synth.workload("ga2048")
     _say(f"full GA batch: {w.B} x N=256, precision={precision}")
-    s, _, got = _run_full(w, precision)
+    s, xy, got = _run_full(w, precision)
     _check_batch_properties(w, got, precision)
-    _check_sample(w, got, _sample(w, 12, 5), precision)
+    _check_sample(w, got, _sample(w, 12, 5), precision, xy)
     if precision == 1:
         it = s.refine_iterations()
         _say(f"  refinement sweeps min/mean/max {it.min()}/{it.mean():.2f}/{it.max()}")
@@ -117,18 +123,18 @@ def test_uneven_batch_4096(precision):
     w = synth.workload("uneven4096")
     _say(f"uneven batch: {w.B} airfoils, N in [{w.n_panels.min()}, {w.n_panels.max()}], K=4, "
          f"precision={precision}")
-    s, _, got = _run_full(w, precision)
+    s, xy, got = _run_full(w, precision)
     _check_batch_properties(w, got, precision)
-    _check_sample(w, got, _sample(w, 12, 6), precision)
+    _check_sample(w, got, _sample(w, 12, 6), precision, xy)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_large_sections_256_n1024(precision):
     w = synth.workload("large256")
     _say(f"large sections: {w.B} x N=1024, K=8, precision={precision}")
-    s, _, got = _run_full(w, precision)
+    s, xy, got = _run_full(w, precision)
     _check_batch_properties(w, got, precision)
-    _check_sample(w, got, _sample(w, 3, 7), precision)
+    _check_sample(w, got, _sample(w, 3, 7), precision, xy)
     if precision == 1:
         it = s.refine_iterations()
         _say(f"  refinement sweeps min/mean/max {it.min()}/{it.mean():.2f}/{it.max()}")
@@ -163,9 +169,8 @@ def test_adjoint_full_batch(name, sample):
         worst_s = max(worst_s, abs(lhs - rhs) / max(scale, abs(rhs)))
     _say(f"  translation invariant {worst_t:.2e}, scaling invariant {worst_s:.2e} over {w.B} airfoils")
     assert worst_t < 1e-10 and worst_s < 1e-10
-    xo, noff_o = oracle.workload_nodes(w)
     for b in _sample(w, sample, 8):
-        xyb = xo[2 * noff_o[b]:2 * noff_o[b + 1]].reshape(-1, 2)
+        xyb = P[2 * noff[b]:2 * noff[b + 1]].reshape(-1, 2)
         with ThreadPoolExecutor(max_workers=8) as ex:
             parts = list(ex.map(lambda a: oracle.cl_gradient(xyb, a), w.alpha[b]))
         ref = sum(dcl[aoff[b] + k] * parts[k] for k in range(len(parts)))
@@ -190,6 +195,6 @@ def _mid_size_workload(B, seed):
 def test_mid_size_batch_more_airfoils_than_cus(precision):
     w = _mid_size_workload(300, 12)
     _say(f"mid-size batch: {w.B} airfoils, N in [{w.n_panels.min()}, {w.n_panels.max()}], precision={precision}")
-    s, _, got = _run_full(w, precision)
+    s, xy, got = _run_full(w, precision)
     _check_batch_properties(w, got, precision)
-    _check_sample(w, got, _sample(w, 3, 13), precision)
+    _check_sample(w, got, _sample(w, 3, 13), precision, xy)
