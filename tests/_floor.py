@@ -9,11 +9,18 @@ spread for one airfoil, from the oracle alone:
   (b) the oracle's LU on the matrix with every influence entry moved by one
       unit in the last place (seeded random direction), which stands for a
       different but correctly rounded evaluation of the entries' logarithms
-      and arctangents.
+      and arctangents;
+  (c) the oracle's LU on the matrix whose influence entries come from a
+      second, equivalent closed form of the same panel integral, written
+      here in numpy with the host's log and atan2: global coordinates, the
+      difference of the two arctangents folded into the angle the panel
+      subtends, log|m - P|^2 per node.  Where a far-field entry is a small
+      difference of large terms, two correct evaluations differ by a few
+      ulp of those terms, not of the entry, and (b) misses that.
 
 Each solution is reduced to (gamma, Cp, Cl, Cl_p) by the oracle's forces and
 compared with the oracle's reference through the relative metrics the parity
-tests use; the floor of a quantity is the larger of the two spreads.  The GPU
+tests use; the floor of a quantity is the largest of the three spreads.  The GPU
 evaluates its entries to within a few ulp of the oracle's and factors in yet
 another order, so its distance to the oracle is expected within a small
 multiple of this floor (FLOOR_FACTOR).
@@ -44,6 +51,32 @@ def metrics(gamma, cp, cl, cl_p, ref):
     )
 
 
+def second_closed_form(P):
+    """Influence block G [N, N] of the panel integral, evaluated as
+    -(1/(4 pi L)) [(d1.h) log|d1|^2 - (d2.h) log|d2|^2 - 2 L^2 + 2 (d1 x d2) theta]
+    with d1 = m_j - P_i, d2 = m_j - P_{i+1}, h = P_{i+1} - P_i and theta the
+    angle the panel subtends at m_j; diagonal (L/2pi)(1 - log(L/2))."""
+    P = np.asarray(P, dtype=np.float64).reshape(-1, 2)
+    N = P.shape[0] - 1
+    m = 0.5 * (P[:-1] + P[1:])
+    h = P[1:] - P[:-1]
+    L2 = (h ** 2).sum(1)
+    L = np.sqrt(L2)
+    d1 = m[:, None, :] - P[None, :-1, :]
+    d2 = m[:, None, :] - P[None, 1:, :]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        l1 = np.log((d1 ** 2).sum(-1))
+        l2 = np.log((d2 ** 2).sum(-1))
+        dot1 = (d1 * h[None]).sum(-1)
+        cr = d1[..., 0] * d2[..., 1] - d1[..., 1] * d2[..., 0]
+        th = np.arctan2(cr, (d1 * d2).sum(-1))
+        G = -(1.0 / (4.0 * np.pi)) / L[None, :] * (dot1 * l1 - (dot1 - L2[None, :]) * l2 - 2.0 * L2[None, :]
+                                                   + 2.0 * cr * th)
+    d = np.arange(N)
+    G[d, d] = L / (2.0 * np.pi) * (1.0 - np.log(0.5 * L))
+    return G
+
+
 def measured_floor(xy, alpha, vinf=1.0, chord=1.0, seed=0) -> dict:
     """Floor of e_gamma, e_Cp, e_Cl, e_Cl_p for one airfoil (nodes [N+1, 2])."""
     xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
@@ -67,9 +100,16 @@ def measured_floor(xy, alpha, vinf=1.0, chord=1.0, seed=0) -> dict:
     if infop != 0:
         raise RuntimeError(f"oracle LU of the perturbed matrix failed (info {infop})")
     X2 = oracle.lu_solve(LUp, pivp, R)
+    # (c) the second closed form of the influence entries
+    Mc = M.copy()
+    Mc[:-1, :-1] = second_closed_form(xy)
+    LUc, pivc, infoc = oracle.lu(Mc)
+    if infoc != 0:
+        raise RuntimeError(f"oracle LU of the second-form matrix failed (info {infoc})")
+    X3 = oracle.lu_solve(LUc, pivc, R)
 
     floor = {}
-    for X in (X1, X2):
+    for X in (X1, X2, X3):
         e = metrics(*oracle.forces(xy, alpha, X, vinf, chord), ref)
         for k, v in e.items():
             floor[k] = max(floor.get(k, 0.0), v)
