@@ -203,6 +203,33 @@ panel_status panel_naca4(int32_t B, const int32_t *node_off, int32_t closed_te,
 panel_status panel_naca4_vjp(int32_t B, const int32_t *node_off, int32_t closed_te,
                              const double *mpt, const double *dxy, double *dmpt, void *stream);
 
+/* Largest workspace panel_solve_noalloc can hold (bytes of the library's
+ * static device scratch array, one per GPU, held until the process ends). */
+#define PANEL_NOALLOC_MAX_BYTES ((size_t)256 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * sequence panel_workspace_init -> panel_assemble -> panel_factor_solve ->
+ * panel_forces in one call, with the workspace in a static device array of
+ * the library instead of caller memory.  Arguments as for those calls; the
+ * caller still provides every input and output array.
+ *  - The plan's workspace (panel_workspace_size) must not exceed
+ *    PANEL_NOALLOC_MAX_BYTES, else PANEL_EINVAL before any HIP call (at
+ *    N = 256 that is about 440 airfoils in FP64, 290 in FP32 + refinement).
+ *  - Allocates nothing and does not synchronise: the plan's metadata is
+ *    copied from host memory owned by the plan on `stream`, so the plan must
+ *    stay alive and unchanged until the call has completed on the stream.
+ *    The first call on a device looks up that device's copy of the array.
+ *  - All calls on one GPU share its array, which keeps the last call's
+ *    contents (nothing in it needs to start at zero): calls that overlap in
+ *    time on one GPU (different streams or threads) race and corrupt each
+ *    other.  Serialise them, or use the caller-owned workspace calls.
+ *  - The workspace stays private: panel_adjoint cannot follow this call.  */
+panel_status panel_solve_noalloc(const panel_plan *plan, const double *xy, const double *alpha,
+                                 const double *chord, double vinf, double refine_tol, int32_t max_iter,
+                                 int32_t *info, double *gamma, double *cp, double *cl, double *cl_p,
+                                 void *stream);
+
 /* Diagnostic: evaluates the FP64 logarithm and two-argument arctangent the
  * assembly and adjoint kernels use (the library's own, not the device libm),
  * for accuracy tests:

@@ -15,6 +15,7 @@ from ._binding import (  # noqa: F401
     PANEL_KMAX,
     PANEL_NMAX,
     PANEL_NMIN,
+    PANEL_NOALLOC_MAX_BYTES,
     PanelError,
     Plan,
     lib_path,
@@ -30,6 +31,7 @@ from ._binding import (  # noqa: F401
     panel_plan_create,
     panel_plan_destroy,
     panel_plan_set_wave_limit,
+    panel_solve_noalloc,
     panel_status_str,
     panel_workspace_init,
     panel_workspace_layout,
@@ -42,5 +44,5 @@ __all__ = [
     "PanelError", "Plan", "PanelSolver", "panel_cl", "panel_cl_cp", "naca_cl",
     "panel_plan_create", "panel_plan_destroy", "panel_plan_set_wave_limit", "panel_workspace_size", "panel_workspace_init", "panel_workspace_layout",
     "panel_assemble", "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
-    "panel_naca4_vjp", "panel_math_eval", "panel_status_str", "panel_last_error", "load_library", "lib_path",
+    "panel_naca4_vjp", "panel_math_eval", "panel_solve_noalloc", "PANEL_NOALLOC_MAX_BYTES", "panel_status_str", "panel_last_error", "load_library", "lib_path",
 ]

@@ -12,6 +12,7 @@ _LIB_PATH = os.path.join(HERE, "libpanel.so")
 PANEL_OK, PANEL_EINVAL, PANEL_ENOMEM, PANEL_EHIP, PANEL_EUNSUPPORTED = range(5)
 PANEL_FP64, PANEL_FP32_REFINE = 0, 1
 PANEL_NMAX, PANEL_NMIN, PANEL_KMAX = 1024, 4, 16
+PANEL_NOALLOC_MAX_BYTES = 256 << 20
 
 _lib = None
 
@@ -50,6 +51,7 @@ def load_library():
     L.panel_naca4.argtypes = [i32, vp, i32, vp, vp, vp]
     L.panel_naca4_vjp.argtypes = [i32, vp, i32, vp, vp, vp, vp]
     L.panel_math_eval.argtypes = [i32, vp, vp, vp, vp, vp]
+    L.panel_solve_noalloc.argtypes = [vp, vp, vp, vp, f64, f64, i32, vp, vp, vp, vp, vp, vp]
     L.panel_status_str.argtypes = [i32]
     L.panel_status_str.restype = C.c_char_p
     L.panel_last_error.argtypes = []
@@ -57,7 +59,7 @@ def load_library():
     for name in ("panel_plan_create", "panel_plan_set_wave_limit", "panel_workspace_size", "panel_workspace_init",
                  "panel_workspace_layout", "panel_assemble",
                  "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
-                 "panel_naca4_vjp", "panel_math_eval"):
+                 "panel_naca4_vjp", "panel_math_eval", "panel_solve_noalloc"):
         getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -207,6 +209,17 @@ def panel_adjoint(plan: Plan, ws, xy, dcl, dcp, dxy, info=None, stream=None):
     _check(load_library().panel_adjoint(plan.handle, _ptr(ws, torch.uint8, "ws"), _ptr(xy, d, "xy"),
                                         _ptr(dcl, d, "dcl"), _ptr(dcp, d, "dcp", True), _ptr(dxy, d, "dxy"),
                                         _ptr(info, torch.int32, "info", True), _stream(stream)))
+
+
+def panel_solve_noalloc(plan: Plan, xy, alpha, chord, vinf, refine_tol, max_iter, info, gamma, cp, cl, cl_p,
+                        stream=None):
+    import torch
+    d = torch.float64
+    _check(load_library().panel_solve_noalloc(plan.handle, _ptr(xy, d, "xy"), _ptr(alpha, d, "alpha"),
+                                              _ptr(chord, d, "chord", True), float(vinf), float(refine_tol),
+                                              int(max_iter), _ptr(info, torch.int32, "info"),
+                                              _ptr(gamma, d, "gamma", True), _ptr(cp, d, "cp", True),
+                                              _ptr(cl, d, "cl"), _ptr(cl_p, d, "cl_p", True), _stream(stream)))
 
 
 def panel_naca4(B, node_off, closed_te, mpt, xy, stream=None):

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -12,6 +13,12 @@
 #include "panel_internal.hpp"
 
 using namespace panel;
+
+// Workspace of panel_solve_noalloc: device memory the library owns, one copy
+// per GPU (allocated when the code object is loaded on that device).  In host
+// code `scratch` names a host-side stand-in, never the device memory: its
+// address on each device comes from hipGetSymbolAddress (scratch_on_device).
+static __device__ __align__(256) unsigned char scratch[PANEL_NOALLOC_MAX_BYTES];
 
 struct panel_plan {
     int32_t B = 0;
@@ -77,6 +84,30 @@ void build_order(panel_plan *p) {
 panel_status check_hip(hipError_t e, const char *what) {
     if (e != hipSuccess)
         return fail(PANEL_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return ok();
+}
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (with that device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+panel_status scratch_on_device(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return check_hip(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(PANEL_EUNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return check_hip(e, "hipGetSymbolAddress(scratch)");
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255u))
+            return fail(PANEL_EHIP, "static scratch has no 256-byte aligned device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
     return ok();
 }
 
@@ -315,6 +346,45 @@ panel_status panel_adjoint(const panel_plan *plan, const void *ws, const double 
     hipError_t e = launch_adjoint(v, plan->B, plan->n_block, plan->max_k, plan->precision == PANEL_FP32_REFINE,
                                   xy, dcl, dcp, dxy, info, static_cast<hipStream_t>(stream));
     return check_hip(e, "adjoint launch");
+}
+
+panel_status panel_solve_noalloc(const panel_plan *plan, const double *xy, const double *alpha,
+                                 const double *chord, double vinf, double refine_tol, int32_t max_iter,
+                                 int32_t *info, double *gamma, double *cp, double *cl, double *cl_p,
+                                 void *stream) {
+    if (!plan || !xy || !alpha || !info || !cl) return fail(PANEL_EINVAL, "NULL argument");
+    if (!aligned8(xy) || !aligned8(alpha) || (chord && !aligned8(chord)) || (gamma && !aligned8(gamma)) ||
+        (cp && !aligned8(cp)) || !aligned8(cl) || (cl_p && !aligned8(cl_p)) ||
+        (reinterpret_cast<uintptr_t>(info) & 3u))
+        return fail(PANEL_EINVAL, "arrays must be aligned (8 bytes; info 4 bytes)");
+    if (!(std::isfinite(vinf) && vinf > 0.0)) return fail(PANEL_EINVAL, "vinf must be finite and > 0");
+    const bool mixed = plan->precision == PANEL_FP32_REFINE;
+    if (mixed) {
+        if (!(std::isfinite(refine_tol) && refine_tol > 0.0))
+            return fail(PANEL_EINVAL, "refine_tol must be finite and > 0");
+        if (max_iter < 0 || max_iter > 100) return fail(PANEL_EINVAL, "max_iter must be in 0..100");
+    }
+    if (plan->layout.total > PANEL_NOALLOC_MAX_BYTES) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf, "plan needs %zu bytes of workspace; the static scratch holds %zu",
+                      plan->layout.total, (size_t)PANEL_NOALLOC_MAX_BYTES);
+        return fail(PANEL_EINVAL, buf);
+    }
+    void *ws = nullptr;
+    panel_status st = scratch_on_device(&ws);
+    if (st != PANEL_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the metadata of this plan (its current airfoil order included), then
+    // the same launches as the caller-owned workspace path
+    hipError_t e = hipMemcpyAsync(ws, plan->blob.data(), plan->blob.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return check_hip(e, "scratch metadata copy");
+    WsView v = ws_view(ws, plan->layout);
+    e = launch_assemble(v, plan->B, plan->max_cols, mixed, xy, alpha, chord, vinf, s);
+    if (e != hipSuccess) return check_hip(e, "assembly launch");
+    e = launch_factor_solve(v, plan->B, plan->n_block, plan->max_n1_block, mixed, refine_tol, max_iter, info, s);
+    if (e != hipSuccess) return check_hip(e, "factor/solve launch");
+    e = launch_forces(v, plan->B, plan->max_k, gamma, cp, cl, cl_p, s);
+    return check_hip(e, "forces launch");
 }
 
 panel_status panel_naca4(int32_t B, const int32_t *node_off, int32_t closed_te, const double *mpt,

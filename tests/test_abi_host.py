@@ -131,3 +131,19 @@ def test_layout_and_status_strings(lib):
     lib.panel_plan_destroy(h)
     for s in range(5):
         assert P.panel_status_str(s).startswith("PANEL_")
+
+
+def test_noalloc_entry_refuses_oversized_plans_before_hip(lib):
+    # 1024 sections at N = 256 need ~600 MB of workspace, more than the
+    # static scratch: refused on the host, before any HIP call.
+    import paper_1511_02166_amd as P
+    noff = np.arange(1025, dtype=np.int32) * 257
+    aoff = np.arange(1025, dtype=np.int32)
+    st, h = _plan(lib, noff, aoff)
+    size = C.c_size_t()
+    assert lib.panel_workspace_size(h, C.byref(size)) == 0 and size.value > P.PANEL_NOALLOC_MAX_BYTES
+    fake = C.c_void_p(0x100000)
+    assert lib.panel_solve_noalloc(h, fake, fake, None, C.c_double(1.0), C.c_double(1e-10), 10, fake,
+                                   None, None, fake, None, None) == P._binding.PANEL_EINVAL
+    assert b"static scratch" in lib.panel_last_error()
+    lib.panel_plan_destroy(h)
