@@ -21,6 +21,11 @@ Parity status per function (see the pins under ``tests/``):
   oracle_force_gradient pinned (central differences of the oracle's Cp and
                         Cl; translation, scaling and rotation invariants of
                         Cp; equals oracle_cl_gradient without cp weights)
+  oracle_hs_*           Hess-Smith formulation (panel_oracle_hs.c): pinned
+                        (velocity integrals by quadrature, cylinder and lifting
+                        cylinder, Joukowski circulation, symmetric sections,
+                        invariances, convergence to the stream-function
+                        scheme's limit)
 """
 from __future__ import annotations
 
@@ -31,7 +36,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = [os.path.join(_HERE, "panel_oracle.c"), os.path.join(_HERE, "panel_oracle_grad.c")]
+_SRC = [os.path.join(_HERE, "panel_oracle.c"), os.path.join(_HERE, "panel_oracle_grad.c"),
+        os.path.join(_HERE, "panel_oracle_hs.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -93,6 +99,20 @@ def lib():
             L.oracle_force_gradient.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_double,
                                                 C.c_double, C.c_void_p, _dp]
             L.oracle_force_gradient.restype = C.c_int
+        L.oracle_hs_influence.argtypes = [_dp, C.c_int, C.c_double, C.c_double, C.c_int] + \
+            [C.POINTER(C.c_double)] * 4
+        L.oracle_hs_influence.restype = None
+        L.oracle_hs_assemble.argtypes = [C.c_int, _dp, C.c_int, _dp, C.c_double, _dp, _dp, _dp]
+        L.oracle_hs_assemble.restype = None
+        L.oracle_hs_forces.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp, _dp, C.c_double, C.c_double,
+                                       _dp, _dp, _dp, _dp]
+        L.oracle_hs_forces.restype = None
+        L.oracle_hs_solve_airfoil.argtypes = [C.c_int, _dp, C.c_int, _dp, C.c_double, C.c_double,
+                                              _dp, _dp, _dp, _dp]
+        L.oracle_hs_solve_airfoil.restype = C.c_int
+        L.oracle_hs_solve_batch.argtypes = [C.c_int, _ip, _dp, _ip, _dp, C.c_void_p, C.c_double,
+                                            _dp, _dp, _dp, _dp, _ip, C.c_int]
+        L.oracle_hs_solve_batch.restype = C.c_int
         _lib = L
     return _lib
 
@@ -171,8 +191,14 @@ def forces(xy, alpha, X, vinf=1.0, chord=1.0):
     return gamma.reshape(K, N), cp.reshape(K, N), cl, clp
 
 
-def solve_airfoil(xy, alpha, vinf=1.0, chord=1.0):
-    """Whole pipeline for one airfoil: dict(gamma[K,N], cp[K,N], cl[K], cl_p[K], info)."""
+FORMULATIONS = ("stream", "hess_smith")
+
+
+def solve_airfoil(xy, alpha, vinf=1.0, chord=1.0, formulation="stream"):
+    """Whole pipeline for one airfoil: dict(gamma[K,N], cp[K,N], cl[K], cl_p[K], info).
+
+    ``gamma`` is the tangential surface speed at the panel midpoints (for the
+    stream-function scheme it equals the sheet strength)."""
     xy = _f64(xy).reshape(-1)
     N = xy.size // 2 - 1
     alpha = _f64(np.atleast_1d(alpha))
@@ -181,11 +207,13 @@ def solve_airfoil(xy, alpha, vinf=1.0, chord=1.0):
     cp = np.zeros(K * N)
     cl = np.zeros(K)
     clp = np.zeros(K)
-    info = lib().oracle_solve_airfoil(N, xy, K, alpha, float(vinf), float(chord), gamma, cp, cl, clp)
+    fn = {"stream": lib().oracle_solve_airfoil, "hess_smith": lib().oracle_hs_solve_airfoil}[formulation]
+    info = fn(N, xy, K, alpha, float(vinf), float(chord), gamma, cp, cl, clp)
     return dict(gamma=gamma.reshape(K, N), cp=cp.reshape(K, N), cl=cl, cl_p=clp, info=info)
 
 
-def solve_batch(xy_flat, node_off, alpha_flat, alpha_off, chord=None, vinf=1.0, nthreads=0):
+def solve_batch(xy_flat, node_off, alpha_flat, alpha_off, chord=None, vinf=1.0, nthreads=0,
+                formulation="stream"):
     """Batch in the packed layout of the GPU library (see panel_oracle.c)."""
     node_off = np.ascontiguousarray(node_off, dtype=np.int32)
     alpha_off = np.ascontiguousarray(alpha_off, dtype=np.int32)
@@ -202,10 +230,33 @@ def solve_batch(xy_flat, node_off, alpha_flat, alpha_off, chord=None, vinf=1.0, 
     if chord is not None:
         chord = _f64(chord)
         ch = chord.ctypes.data_as(C.c_void_p)
-    used = lib().oracle_solve_batch(B, node_off, _f64(xy_flat).reshape(-1), alpha_off,
-                                    _f64(alpha_flat), ch, float(vinf), gamma, cp, cl, clp, info,
-                                    int(nthreads))
+    fn = {"stream": lib().oracle_solve_batch, "hess_smith": lib().oracle_hs_solve_batch}[formulation]
+    used = fn(B, node_off, _f64(xy_flat).reshape(-1), alpha_off, _f64(alpha_flat), ch, float(vinf), gamma, cp, cl,
+              clp, info, int(nthreads))
     return dict(gamma=gamma, cp=cp, cl=cl, cl_p=clp, info=info, threads=used)
+
+
+def hs_influence(xy, i, x, y, self_point=False):
+    """Hess-Smith velocities at (x, y) of panel i: unit source (sx, sy), unit
+    counter-clockwise vortex (wx, wy)."""
+    out = [C.c_double() for _ in range(4)]
+    lib().oracle_hs_influence(_f64(xy).reshape(-1), int(i), float(x), float(y), int(bool(self_point)),
+                              *[C.byref(o) for o in out])
+    return tuple(o.value for o in out)
+
+
+def hs_assemble(xy, alpha, vinf=1.0):
+    """Hess-Smith system: M [(N+1),(N+1)], right-hand sides R [K, N+1] and the
+    tangential-velocity matrix Mt [N, N+1]."""
+    xy = _f64(xy).reshape(-1)
+    N = xy.size // 2 - 1
+    alpha = _f64(np.atleast_1d(alpha))
+    K = alpha.size
+    M = np.zeros((N + 1) * (N + 1))
+    R = np.zeros((N + 1) * K)
+    Mt = np.zeros((N + 1) * (N + 1))
+    lib().oracle_hs_assemble(N, xy, K, alpha, float(vinf), M, R, Mt)
+    return M.reshape(N + 1, N + 1), R.reshape(K, N + 1), Mt.reshape(N + 1, N + 1)[:N]
 
 
 def cl_gradient(xy, alpha, vinf=1.0, chord=1.0, with_alpha=False):
