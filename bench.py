@@ -66,7 +66,10 @@ def _args():
     ap.add_argument("--no-side", action="store_true", help="skip the uneven and large-panel batches")
     ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of a graph replay")
     ap.add_argument("--wave-limit", type=int, default=None,
-                    help="largest system order for the one-wavefront LU (0 = workgroup LU only)")
+                    help="largest system order for the one-wavefront LU (0 = workgroup LU only); "
+                         "implies --no-autotune")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tiling instead of timing the candidates first")
     return ap.parse_args()
 
 
@@ -109,7 +112,9 @@ def main():
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream()
 
-    def setup(name, batch=None, wave_limit=None):
+    tuned = {}
+
+    def setup(name, batch=None, wave_limit=None, tune=True):
         w = synth.workload(name, B=batch)
         noff, aoff = w.node_offsets(), w.alpha_offsets()
         alpha = torch.as_tensor(w.alpha_flat(), device=dev)
@@ -117,6 +122,12 @@ def main():
         s32 = P.PanelSolver(noff, aoff, P.PANEL_FP32_REFINE, wave_limit=wave_limit)
         xy = s64.naca4(torch.as_tensor(w.mpt(), device=dev), True)
         torch.cuda.synchronize()
+        if tune and wave_limit is None and not a.no_autotune:
+            # the tiling search (untimed): per candidate one warm-up and three steps
+            for tag, s in (("fp64", s64), ("fp32_refine", s32)):
+                times = s.autotune(xy, alpha)
+                tuned[f"{name}/{tag}"] = {"tiling": s.tiling,
+                                          "candidates_ms": {str(list(k)): round(v, 4) for k, v in times.items()}}
         return w, xy, alpha, s64, s32
 
     def eager(solver, xy, alpha, steps, warmup, tol=1e-10, max_iter=10):
@@ -201,7 +212,7 @@ def main():
     # adjoint on its own workload: 1024 sections at 6 degrees, FP64 forward
     adj = None
     if not a.no_adjoint:
-        wa, xya, ala, sa, _ = setup("adjoint1024")
+        wa, xya, ala, sa, _ = setup("adjoint1024", tune=False)
         dcl = torch.ones(wa.B, dtype=torch.float64, device=dev)
         dxy = torch.empty_like(xya)
         fwd = replay(sa, xya, ala, a.steps, a.warmup, False)
@@ -305,6 +316,7 @@ def main():
         "roofline": roof,
         "roofline_kernels": kern,
         "other_workloads": side,
+        "tiling": tuned,
     }
 
     if not a.no_cpu_baseline:

@@ -68,6 +68,17 @@ typedef enum {
                                iterative refinement of the solution          */
 } panel_precision;
 
+typedef enum {
+    PANEL_STREAM_FUNCTION = 0,  /* Sec. 2: constant-density vortex sheet on each
+                                   panel, stream function constant on the
+                                   contour, Kutta row gamma_0 + gamma_{N-1} = 0 */
+    PANEL_HESS_SMITH = 1        /* constant source density per panel plus one
+                                   vortex density shared by all panels, flow
+                                   tangency at the midpoints, Kutta row: equal
+                                   and opposite tangential speeds on the two
+                                   trailing-edge panels                         */
+} panel_formulation;
+
 /* Largest supported panel count per airfoil. */
 #define PANEL_NMAX 1024
 /* Smallest supported panel count per airfoil. */
@@ -105,6 +116,45 @@ void panel_plan_destroy(panel_plan *plan);
  * panel_adjoint return PANEL_EINVAL until it has run.  PANEL_EINVAL
  * outside the range.                                                       */
 panel_status panel_plan_set_wave_limit(panel_plan *plan, int32_t max_n1);
+
+/* Select the panel formulation (default PANEL_STREAM_FUNCTION).  Both give
+ * an (N_b + 1) x (N_b + 1) system per airfoil, factored and solved alike.
+ * PANEL_HESS_SMITH unknowns: the N_b source densities, then the vortex
+ * density; its workspace also keeps the tangential-velocity influence
+ * matrix (one more system-sized section), so call this before
+ * panel_workspace_size.  panel_forces reports, for both, the tangential
+ * surface speed at the panel midpoints (the `gamma` output), Cp, Cl from the
+ * circulation -2 sum_i u_i L_i / (vinf c) and Cl_p.  panel_adjoint supports
+ * the stream-function formulation only (PANEL_EUNSUPPORTED otherwise).     */
+panel_status panel_plan_set_formulation(panel_plan *plan, int32_t formulation);
+
+/* How the factorisation maps a batch onto the GPU (Sec. 3: many independent
+ * dense systems; Sec. 4 splits the population into slices, here the batch
+ * is one queue).  This is the entry of the tile table that the Python
+ * autotuner (PanelSolver.autotune) fills by timing candidates per batch.
+ *   wave_max_n1  systems with n1 <= wave_max_n1 (0..320) are factored by one
+ *                wavefront each, larger ones by a workgroup each
+ *   persistent   1: one launch of persistent workgroups pops the airfoils in
+ *                LPT order, whole workgroups taking the large systems and
+ *                single wavefronts the rest, and (PANEL_FP32_REFINE) refines
+ *                each solution right after its factorisation; 0: one launch
+ *                per kernel family.  Batches with systems above 768 rows, or
+ *                wg_waves = 8, always take separate launches.
+ *   wg_waves     wavefronts per workgroup-factored system: 4, 8, or 0 (eight
+ *                when the batch has at most one airfoil per CU; systems above
+ *                768 rows always take eight)
+ * Default {320, 0, 0} (the faster choice on the batches measured; the
+ * persistent kernel holds both paths and spills more registers).  Changing
+ * wave_max_n1 takes effect at the next panel_workspace_init, as for
+ * panel_plan_set_wave_limit.                                               */
+typedef struct {
+    int32_t wave_max_n1;
+    int32_t persistent;
+    int32_t wg_waves;
+} panel_tiling;
+
+panel_status panel_plan_set_tiling(panel_plan *plan, const panel_tiling *tiling);
+panel_status panel_plan_get_tiling(const panel_plan *plan, panel_tiling *tiling);
 
 /* Bytes of device workspace the plan needs (256-byte aligned base). */
 panel_status panel_workspace_size(const panel_plan *plan, size_t *bytes);

@@ -30,6 +30,8 @@ from ._binding import (  # noqa: F401
     panel_naca4_vjp,
     panel_plan_create,
     panel_plan_destroy,
+    panel_plan_get_tiling,
+    panel_plan_set_tiling,
     panel_plan_set_wave_limit,
     panel_solve_noalloc,
     panel_status_str,
@@ -37,12 +39,13 @@ from ._binding import (  # noqa: F401
     panel_workspace_layout,
     panel_workspace_size,
 )
-from .solver import PanelSolver, naca_cl, panel_cl, panel_cl_cp  # noqa: F401
+from .solver import PanelSolver, TileTable, naca_cl, panel_cl, panel_cl_cp  # noqa: F401
 
 __all__ = [
     "PANEL_FP64", "PANEL_FP32_REFINE", "PANEL_NMAX", "PANEL_NMIN", "PANEL_KMAX",
-    "PanelError", "Plan", "PanelSolver", "panel_cl", "panel_cl_cp", "naca_cl",
-    "panel_plan_create", "panel_plan_destroy", "panel_plan_set_wave_limit", "panel_workspace_size", "panel_workspace_init", "panel_workspace_layout",
+    "PanelError", "Plan", "PanelSolver", "TileTable", "panel_cl", "panel_cl_cp", "naca_cl",
+    "panel_plan_create", "panel_plan_destroy", "panel_plan_set_wave_limit", "panel_plan_set_tiling",
+    "panel_plan_get_tiling", "panel_workspace_size", "panel_workspace_init", "panel_workspace_layout",
     "panel_assemble", "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
     "panel_naca4_vjp", "panel_math_eval", "panel_solve_noalloc", "PANEL_NOALLOC_MAX_BYTES", "panel_status_str", "panel_last_error", "load_library", "lib_path",
 ]

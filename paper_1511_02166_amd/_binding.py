@@ -17,6 +17,14 @@ PANEL_NOALLOC_MAX_BYTES = 256 << 20
 _lib = None
 
 
+class panel_tiling(C.Structure):
+    """Mirror of the C struct panel_tiling (see include/panel.h)."""
+    _fields_ = [("wave_max_n1", C.c_int32), ("persistent", C.c_int32), ("wg_waves", C.c_int32)]
+
+    def as_dict(self):
+        return dict(wave_max_n1=int(self.wave_max_n1), persistent=int(self.persistent), wg_waves=int(self.wg_waves))
+
+
 class PanelError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{panel_status_str(status)}: {msg}")
@@ -41,6 +49,8 @@ def load_library():
     L.panel_plan_destroy.argtypes = [vp]
     L.panel_plan_destroy.restype = None
     L.panel_plan_set_wave_limit.argtypes = [vp, i32]
+    L.panel_plan_set_tiling.argtypes = [vp, C.POINTER(panel_tiling)]
+    L.panel_plan_get_tiling.argtypes = [vp, C.POINTER(panel_tiling)]
     L.panel_workspace_size.argtypes = [vp, C.POINTER(sz)]
     L.panel_workspace_init.argtypes = [vp, vp, vp]
     L.panel_workspace_layout.argtypes = [vp, i32, vp]
@@ -56,7 +66,8 @@ def load_library():
     L.panel_status_str.restype = C.c_char_p
     L.panel_last_error.argtypes = []
     L.panel_last_error.restype = C.c_char_p
-    for name in ("panel_plan_create", "panel_plan_set_wave_limit", "panel_workspace_size", "panel_workspace_init",
+    for name in ("panel_plan_create", "panel_plan_set_wave_limit", "panel_plan_set_tiling", "panel_plan_get_tiling",
+                 "panel_workspace_size", "panel_workspace_init",
                  "panel_workspace_layout", "panel_assemble",
                  "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
                  "panel_naca4_vjp", "panel_math_eval", "panel_solve_noalloc"):
@@ -165,6 +176,18 @@ def panel_plan_destroy(plan: Plan):
 def panel_plan_set_wave_limit(plan: Plan, max_n1: int):
     """Largest system order factored by one wavefront (0..320; 0 = none)."""
     _check(load_library().panel_plan_set_wave_limit(plan.handle, int(max_n1)))
+
+
+def panel_plan_set_tiling(plan: Plan, wave_max_n1: int, persistent: int, wg_waves: int):
+    """Kernel mapping of the factorisation (see panel_tiling in include/panel.h)."""
+    t = panel_tiling(int(wave_max_n1), int(persistent), int(wg_waves))
+    _check(load_library().panel_plan_set_tiling(plan.handle, C.byref(t)))
+
+
+def panel_plan_get_tiling(plan: Plan) -> dict:
+    t = panel_tiling()
+    _check(load_library().panel_plan_get_tiling(plan.handle, C.byref(t)))
+    return t.as_dict()
 
 
 def panel_workspace_size(plan: Plan) -> int:

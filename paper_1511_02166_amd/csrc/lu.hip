@@ -21,8 +21,10 @@
 // factorisation they hold L^{-1} P b; the same workgroup then finishes with
 // the back substitution (blocked: one wavefront solves each 64-row diagonal
 // block with shuffles, all of them update the rows above).
+#include <algorithm>
 #include <climits>
 
+#include "lu_wave_impl.hpp"
 #include "panel_internal.hpp"
 #include "wave.hpp"
 
@@ -71,6 +73,7 @@ template <> __device__ inline float *sys_base<float>(const WsView &v, const Airf
 // derived from it are formed where they are used instead of being hoisted
 // to the start of the kernel and kept (or spilled) across every phase.
 __device__ __forceinline__ int opaque_s(int v) {
+    v = __builtin_amdgcn_readfirstlane(v);   // uniform by contract (free if already scalar)
     asm volatile("" : "+s"(v));
     return v;
 }
@@ -454,9 +457,17 @@ __device__ __forceinline__ void gemm_sub(T *A, int ld, int rowA, int rowEnd, int
 // per thread in a panel (n1 <= TB * RMAX).  With 256 threads and up to three
 // rows per thread two workgroups share a CU; the other instances take the
 // whole register file of one.
+// LDS of one workgroup's factorisation.
+template <typename T, int NB, int RMAX, int TB> struct WgLuLds {
+    PanelLds<T, NB, RMAX, TB> L;
+    T s_L11[NB][NB + 1];
+    T s_U[NB][CH + 4];   // also holds the CT x (SP + 1) band of step 6
+    T y[PANEL_NMAX + 1];
+};
+
 template <typename T, int NB, int RMAX, int TB>
-__global__ __launch_bounds__(TB, (TB <= 256 && RMAX <= 3) ? 2 : 1) void lu_kernel(WsView v, int32_t *__restrict__ info_out) {
-    const int b = v.order[blockIdx.x];
+__device__ __forceinline__ void wg_lu(const WsView &v, int b, int32_t *__restrict__ info_out,
+                                      WgLuLds<T, NB, RMAX, TB> &S) {
     const AirfoilMeta mt = v.meta[b];
     const int n = mt.n1, ld = mt.ld, ncols = mt.n1 + mt.K;
     const int tid = threadIdx.x;
@@ -471,9 +482,9 @@ __global__ __launch_bounds__(TB, (TB <= 256 && RMAX <= 3) ? 2 : 1) void lu_kerne
     T *A = sys_base<T>(v, mt);
     int32_t *piv = v.piv + mt.piv_off;
 
-    __shared__ PanelLds<T, NB, RMAX, TB> L;
-    __shared__ T s_L11[NB][NB + 1];
-    __shared__ T s_U[NB][CH + 4];   // also holds the CT x (SP + 1) band of step 6
+    PanelLds<T, NB, RMAX, TB> &L = S.L;
+    T (*s_L11)[NB + 1] = S.s_L11;
+    T (*s_U)[CH + 4] = S.s_U;
     int info = 0;
 
     // Super-panels of SP columns; inside, NB-column pivot panels update the
@@ -568,7 +579,7 @@ __global__ __launch_bounds__(TB, (TB <= 256 && RMAX <= 3) ? 2 : 1) void lu_kerne
         for (int i = tid; i < n * mt.K; i += TB) X[i] = __builtin_nan("");
         return;
     }
-    __shared__ T y[PANEL_NMAX + 1];
+    T *y = S.y;
     T *sblk = &s_U[0][0];   // SB x SB values (NB * CH >= SB * SB)
     for (int k = 0; k < mt.K; ++k) {
         __syncthreads();
@@ -579,6 +590,12 @@ __global__ __launch_bounds__(TB, (TB <= 256 && RMAX <= 3) ? 2 : 1) void lu_kerne
     }
 }
 
+template <typename T, int NB, int RMAX, int TB>
+__global__ __launch_bounds__(TB, (TB <= 256 && RMAX <= 3) ? 2 : 1) void lu_kernel(WsView v, int32_t *__restrict__ info_out) {
+    __shared__ WgLuLds<T, NB, RMAX, TB> S;
+    wg_lu<T, NB, RMAX, TB>(v, v.order[blockIdx.x], info_out, S);
+}
+
 // Mixed precision: iterative refinement of X with the FP64 system in A64 and
 // the FP32 factors in A32.  One sweep: r = b - A x in FP64 (one pass over A
 // serving KG right-hand sides); for each right-hand side not yet converged:
@@ -586,11 +603,19 @@ __global__ __launch_bounds__(TB, (TB <= 256 && RMAX <= 3) ? 2 : 1) void lu_kerne
 // ||A||_inf ||x||_inf (no further sweep can improve x); otherwise
 // d = U^{-1} L^{-1} P r in FP32, x += d, and stop once ||d||_inf <= tol
 // ||x||_inf.
+constexpr int KG = 2;   // right-hand sides refined per pass over A
+template <int TB> struct WgRefLds {
+    double sx[KG][PANEL_NMAX + 1];
+    double sr[KG][PANEL_NMAX + 1];
+    float sd[PANEL_NMAX + 1];
+    int perm[PANEL_NMAX + 1];
+    double red[3][TB / 64];
+    float sblk[SB * SB];
+};
+
 template <int TB>
-__global__ __launch_bounds__(TB) void refine_kernel(WsView v, int32_t *__restrict__ info, double tol,
-                                                     int max_iter) {
-    constexpr int KG = 2;
-    const int b = v.order[blockIdx.x];
+__device__ __forceinline__ void wg_refine(const WsView &v, int b, int32_t *__restrict__ info, double tol,
+                                          int max_iter, WgRefLds<TB> &S) {
     const AirfoilMeta mt = v.meta[b];
     const int n = mt.n1, ld = mt.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -605,12 +630,12 @@ __global__ __launch_bounds__(TB) void refine_kernel(WsView v, int32_t *__restric
     const float *LU = v.a32 + mt.a_off;
     const int32_t *piv = v.piv + mt.piv_off;
     double *X = v.x + mt.x_off;
-    __shared__ double sx[KG][PANEL_NMAX + 1];
-    __shared__ double sr[KG][PANEL_NMAX + 1];
-    __shared__ float sd[PANEL_NMAX + 1];
-    __shared__ int perm[PANEL_NMAX + 1];
-    __shared__ double red[3][TB / 64];
-    __shared__ float sblk[SB * SB];
+    double (*sx)[PANEL_NMAX + 1] = S.sx;
+    double (*sr)[PANEL_NMAX + 1] = S.sr;
+    float *sd = S.sd;
+    int *perm = S.perm;
+    double (*red)[TB / 64] = S.red;
+    float *sblk = S.sblk;
     if (tid == 0) {
         for (int i = 0; i < n; ++i) perm[i] = i;
         for (int i = 0; i < n; ++i) {
@@ -743,6 +768,92 @@ __global__ __launch_bounds__(TB) void refine_kernel(WsView v, int32_t *__restric
     }
 }
 
+template <int TB>
+__global__ __launch_bounds__(TB) void refine_kernel(WsView v, int32_t *__restrict__ info, double tol,
+                                                     int max_iter) {
+    __shared__ WgRefLds<TB> S;
+    wg_refine<TB>(v, v.order[blockIdx.x], info, tol, max_iter, S);
+}
+
+// One launch for a whole batch: persistent workgroups of four wavefronts pop
+// airfoils from the plan's LPT order.  The first n_block entries (the largest
+// systems) are taken by whole workgroups; once those are gone every
+// wavefront pops the smaller systems on its own.  With FP32 factors each
+// airfoil's FP64 refinement follows its factorisation in the same workgroup
+// or wavefront, so the mixed-precision factor/solve is one launch too.
+template <typename T> struct BatchWaveLds {
+    union {
+        wv::WaveLuLds<T> lu;
+        wv::WaveRefLds ref;
+    } u;
+};
+template <typename T> union BatchLds {
+    WgLuLds<T, 16, 3, TPB> lu;
+    WgRefLds<TPB> ref;
+    BatchWaveLds<T> wave[TPB / 64];
+};
+
+// One item of each kind.  (Kept out of line, with separate register
+// allocations, they spilled more: 600-1000 bytes of scratch per function on
+// gfx950 against 216-424 for the whole kernel inlined.)
+template <typename T>
+__device__ __forceinline__ void batch_wg_item(const WsView &v, int b, int32_t *info, int mixed, double tol,
+                                           int max_iter, BatchLds<T> &S) {
+    wg_lu<T, 16, 3, TPB>(v, b, info, S.lu);
+    __syncthreads();
+    if (mixed) {
+        wg_refine<TPB>(v, b, info, tol, max_iter, S.ref);
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void batch_wave_item(const WsView &v, int b, int32_t *info, int mixed, double tol,
+                                             int max_iter, BatchWaveLds<T> &W) {
+    wv::wave_lu<T>(v, b, info, W.u.lu);
+    wv::wave_sync();
+    if (mixed) {
+        wv::wave_refine(v, b, info, tol, max_iter, W.u.ref);
+        wv::wave_sync();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB, 2) void batch_kernel(WsView v, int32_t n_block, int32_t B, int32_t mixed,
+                                                       double tol, int32_t max_iter, int32_t *__restrict__ info) {
+    __shared__ BatchLds<T> S;
+    __shared__ int s_item;
+    int32_t *q = v.queue;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&q[0], 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);   // uniform: keep it scalar
+        __syncthreads();
+        if (it >= n_block) break;
+        batch_wg_item<T>(v, v.order[it], info, mixed, tol, max_iter, S);
+    }
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // this wavefront's LDS area
+    for (;;) {
+        int it = 0;
+        if ((threadIdx.x & 63) == 0) it = atomicAdd(&q[1], 1);
+        it = __builtin_amdgcn_readfirstlane(it);   // lane 0's ticket, in a scalar register
+        if (it >= B - n_block) break;
+        batch_wave_item<T>(v, v.order[n_block + it], info, mixed, tol, max_iter, S.wave[w]);
+    }
+    // every workgroup counts itself out; the last one leaves the counters at
+    // zero for the next launch on this workspace
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&q[2], 1) == (int)gridDim.x - 1) {
+            q[0] = 0;
+            q[1] = 0;
+            q[2] = 0;
+            __threadfence();
+        }
+    }
+}
+
 // Compute units of the current device (read once per process and device).
 int device_cus() {
     static int cus[64] = {0};
@@ -756,14 +867,23 @@ int device_cus() {
     return cus[dev];
 }
 
-// With at most one airfoil per CU, eight wavefronts per airfoil (the whole
-// CU) beat four (measured: 256 sections at N = 1024, 24.4 -> 19.9 ms in
-// FP64); with more airfoils than CUs, four per airfoil and two airfoils per
-// CU keep more systems in flight (4096 airfoils, N = 96..512: 17.2 ms
-// against 22.6).  Systems of more than 768 rows always take eight.
+// Eight wavefronts per airfoil for the workgroup kernels: by default when
+// the batch has at most one airfoil per CU (measured: 256 sections at
+// N = 1024, 24.4 -> 19.9 ms in FP64; with more airfoils than CUs, four per
+// airfoil and two airfoils per CU keep more systems in flight: 4096
+// airfoils, N = 96..512, 17.2 ms against 22.6), and always for systems of
+// more than 768 rows.
+bool eight_waves(int32_t n_block, int32_t max_n1, int32_t wg_waves) {
+    if (max_n1 > 3 * TPB) return true;
+    if (wg_waves == 4) return false;
+    if (wg_waves == 8) return true;
+    return n_block <= device_cus();
+}
+
 template <typename T>
-hipError_t launch_lu_any(const WsView &v, int32_t B, int32_t max_n1, int32_t *info, hipStream_t s) {
-    if (B <= device_cus() || max_n1 > 3 * TPB)
+hipError_t launch_lu_any(const WsView &v, int32_t B, int32_t max_n1, int32_t wg_waves, int32_t *info,
+                         hipStream_t s) {
+    if (eight_waves(B, max_n1, wg_waves))
         lu_kernel<T, 16, 3, 512><<<B, 512, 0, s>>>(v, info);   // n1 <= 1536
     else
         lu_kernel<T, 16, 3, TPB><<<B, TPB, 0, s>>>(v, info);
@@ -774,11 +894,20 @@ hipError_t launch_lu_any(const WsView &v, int32_t B, int32_t max_n1, int32_t *in
 
 hipError_t launch_factor_solve(const WsView &v, int32_t B, int32_t n_block, int32_t max_n1_block,
                                int32_t mixed, double tol, int32_t max_iter, int32_t *info,
-                               hipStream_t stream) {
+                               int32_t persistent, int32_t wg_waves, hipStream_t stream) {
     hipError_t e = hipSuccess;
+    if (persistent && (n_block == 0 || !eight_waves(n_block, max_n1_block, wg_waves == 0 ? 4 : wg_waves))) {
+        const int n_small = B - n_block;
+        const int grid = std::min(2 * device_cus(), n_block + (n_small + TPB / 64 - 1) / (TPB / 64));
+        if (mixed)
+            batch_kernel<float><<<grid, TPB, 0, stream>>>(v, n_block, B, 1, tol, max_iter, info);
+        else
+            batch_kernel<double><<<grid, TPB, 0, stream>>>(v, n_block, B, 0, tol, max_iter, info);
+        return hipGetLastError();
+    }
     if (n_block > 0) {
-        e = mixed ? launch_lu_any<float>(v, n_block, max_n1_block, info, stream)
-                  : launch_lu_any<double>(v, n_block, max_n1_block, info, stream);
+        e = mixed ? launch_lu_any<float>(v, n_block, max_n1_block, wg_waves, info, stream)
+                  : launch_lu_any<double>(v, n_block, max_n1_block, wg_waves, info, stream);
         if (e != hipSuccess) return e;
     }
     e = launch_lu_wave(v, n_block, B - n_block, mixed, info, stream);
@@ -786,7 +915,7 @@ hipError_t launch_factor_solve(const WsView &v, int32_t B, int32_t n_block, int3
     if (mixed) {
         if (n_block > 0) {
             // the same choice of workgroup size as for the factorisation
-            if (n_block <= device_cus() || max_n1_block > 3 * TPB)
+            if (eight_waves(n_block, max_n1_block, wg_waves))
                 refine_kernel<512><<<n_block, 512, 0, stream>>>(v, info, tol, max_iter);
             else
                 refine_kernel<TPB><<<n_block, TPB, 0, stream>>>(v, info, tol, max_iter);

@@ -26,7 +26,7 @@ struct panel_plan {
     int32_t max_n1 = 0;
     int32_t max_k = 0;
     int32_t max_cols = 0;  // max over airfoils of n1 + K
-    int32_t wave_max_n1 = PANEL_WAVE_MAX_N1;  // largest order given to the one-wavefront LU
+    panel_tiling tiling{PANEL_WAVE_MAX_N1, 0, 0};  // wave_max_n1: largest order given to the one-wavefront LU
     int32_t n_block = 0;       // airfoils factored by the workgroup LU (first in order)
     int32_t max_n1_block = 0;  // their largest order
     // set when the wave limit changed after the last panel_workspace_init:
@@ -34,6 +34,10 @@ struct panel_plan {
     mutable bool order_stale = false;
     std::vector<int32_t> node_off, alpha_off;
     std::vector<double> cost;  // LPT key: (2/3) n1^3 + 2 n1^2 K
+    int32_t formulation = PANEL_STREAM_FUNCTION;
+    int32_t max_ld = 0;
+    int64_t a_total = 0;       // elements of one system section (all airfoils)
+    int64_t x_total = 0, piv_total = 0;
     std::vector<char> blob;  // header | meta | order, copied by workspace_init
     WsLayout layout{};
 };
@@ -56,6 +60,49 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
+// Byte offsets of the workspace sections for the plan's batch, precision and
+// formulation.
+void compute_layout(panel_plan *p) {
+    const int32_t B = p->B;
+    WsLayout &l = p->layout;
+    size_t off = align256(sizeof(WsHeader));
+    l.meta = off;
+    off = align256(off + sizeof(AirfoilMeta) * B);
+    l.order = off;
+    off = align256(off + sizeof(int32_t) * B);
+    l.queue = off;   // inside the metadata copy: zero after panel_workspace_init
+    off = align256(off + sizeof(int32_t) * 4);
+    l.flag = off;
+    off = align256(off + sizeof(int32_t) * B);
+    l.chord = off;
+    off = align256(off + sizeof(double) * B);
+    l.alpha = off;
+    off = align256(off + sizeof(double) * p->alpha_off[B]);
+    l.geom = off;
+    off = align256(off + sizeof(PanelGeom) * (size_t(p->node_off[B]) - B));
+    l.a64 = off;
+    off = align256(off + sizeof(double) * size_t(p->a_total));
+    if (p->precision == PANEL_FP32_REFINE) {
+        l.a32 = off;
+        off = align256(off + sizeof(float) * size_t(p->a_total));
+    } else {
+        l.a32 = 0;
+    }
+    if (p->formulation == PANEL_HESS_SMITH) {
+        l.tg = off;
+        off = align256(off + sizeof(double) * size_t(p->a_total));
+    } else {
+        l.tg = 0;
+    }
+    l.x = off;
+    off = align256(off + sizeof(double) * size_t(p->x_total));
+    l.piv = off;
+    off = align256(off + sizeof(int32_t) * size_t(p->piv_total));
+    l.iters = off;
+    off = align256(off + sizeof(int32_t) * B);
+    l.total = off;
+}
+
 // Airfoils for the workgroup LU first, then those for the one-wavefront LU;
 // each group by decreasing cost (longest processing time first), so the
 // in-order dispatch of workgroups is an LPT list schedule within each launch.
@@ -68,7 +115,7 @@ void build_order(panel_plan *p) {
     for (int32_t b = 0; b < B; ++b) {
         order[b] = b;
         const int32_t n1 = p->node_off[b + 1] - p->node_off[b];
-        big[b] = n1 > p->wave_max_n1;
+        big[b] = n1 > p->tiling.wave_max_n1;
         if (big[b]) {
             ++p->n_block;
             p->max_n1_block = std::max(p->max_n1_block, n1);
@@ -187,44 +234,20 @@ panel_status panel_plan_create(int32_t B, const int32_t *h_node_offsets,
             p->max_n1 = std::max(p->max_n1, m.n1);
             p->max_k = std::max(p->max_k, m.K);
             p->max_cols = std::max(p->max_cols, m.n1 + m.K);
+            p->max_ld = std::max(p->max_ld, m.ld);
             double n = m.n1;
             cost[b] = n * n * n / 1.5 + 2.0 * n * n * m.K;
         }
-        WsLayout &l = p->layout;
-        size_t off = align256(sizeof(WsHeader));
-        l.meta = off;
-        off = align256(off + sizeof(AirfoilMeta) * B);
-        l.order = off;
-        off = align256(off + sizeof(int32_t) * B);
-        l.flag = off;
-        off = align256(off + sizeof(int32_t) * B);
-        l.chord = off;
-        off = align256(off + sizeof(double) * B);
-        l.alpha = off;
-        off = align256(off + sizeof(double) * h_alpha_offsets[B]);
-        l.geom = off;
-        off = align256(off + sizeof(PanelGeom) * (size_t(h_node_offsets[B]) - B));
-        l.a64 = off;
-        off = align256(off + sizeof(double) * size_t(a_off));
-        if (precision == PANEL_FP32_REFINE) {
-            l.a32 = off;
-            off = align256(off + sizeof(float) * size_t(a_off));
-        } else {
-            l.a32 = 0;
-        }
-        l.x = off;
-        off = align256(off + sizeof(double) * size_t(x_off));
-        l.piv = off;
-        off = align256(off + sizeof(int32_t) * size_t(piv_off));
-        l.iters = off;
-        off = align256(off + sizeof(int32_t) * B);
-        l.total = off;
-
+        p->a_total = a_off;
+        p->x_total = x_off;
+        p->piv_total = piv_off;
+        compute_layout(p);
         WsHeader hdr{};
         hdr.vinf = 1.0;
         hdr.B = B;
         hdr.precision = precision;
         hdr.max_n1 = p->max_n1;
+        const WsLayout &l = p->layout;
         p->blob.assign(l.flag, 0);
         std::memcpy(p->blob.data(), &hdr, sizeof hdr);
         std::memcpy(p->blob.data() + l.meta, meta.data(), sizeof(AirfoilMeta) * B);
@@ -246,11 +269,38 @@ panel_status panel_plan_set_wave_limit(panel_plan *plan, int32_t max_n1) {
         std::snprintf(buf, sizeof buf, "wave limit must be in 0..%d", PANEL_WAVE_MAX_N1);
         return fail(PANEL_EINVAL, buf);
     }
-    if (max_n1 != plan->wave_max_n1) {
-        plan->wave_max_n1 = max_n1;
+    if (max_n1 != plan->tiling.wave_max_n1) {
+        plan->tiling.wave_max_n1 = max_n1;
         build_order(plan);
         plan->order_stale = true;
     }
+    return ok();
+}
+
+panel_status panel_plan_set_tiling(panel_plan *plan, const panel_tiling *t) {
+    if (!plan || !t) return fail(PANEL_EINVAL, "NULL argument");
+    if (t->persistent != 0 && t->persistent != 1) return fail(PANEL_EINVAL, "persistent must be 0 or 1");
+    if (t->wg_waves != 0 && t->wg_waves != 4 && t->wg_waves != 8)
+        return fail(PANEL_EINVAL, "wg_waves must be 0, 4 or 8");
+    panel_status st = panel_plan_set_wave_limit(plan, t->wave_max_n1);
+    if (st != PANEL_OK) return st;
+    plan->tiling.persistent = t->persistent;
+    plan->tiling.wg_waves = t->wg_waves;
+    return ok();
+}
+
+panel_status panel_plan_set_formulation(panel_plan *plan, int32_t formulation) {
+    if (!plan) return fail(PANEL_EINVAL, "NULL plan");
+    if (formulation != PANEL_STREAM_FUNCTION && formulation != PANEL_HESS_SMITH)
+        return fail(PANEL_EINVAL, "unknown formulation");
+    plan->formulation = formulation;
+    compute_layout(plan);
+    return ok();
+}
+
+panel_status panel_plan_get_tiling(const panel_plan *plan, panel_tiling *t) {
+    if (!plan || !t) return fail(PANEL_EINVAL, "NULL argument");
+    *t = plan->tiling;
     return ok();
 }
 
@@ -298,8 +348,12 @@ panel_status panel_assemble(const panel_plan *plan, const double *xy, const doub
     if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(PANEL_EINVAL, "workspace must be 256-byte aligned");
     if (!(std::isfinite(vinf) && vinf > 0.0)) return fail(PANEL_EINVAL, "vinf must be finite and > 0");
     WsView v = ws_view(ws, plan->layout);
-    hipError_t e = launch_assemble(v, plan->B, plan->max_cols, plan->precision == PANEL_FP32_REFINE,
-                                   xy, alpha, chord, vinf, static_cast<hipStream_t>(stream));
+    const bool mixed = plan->precision == PANEL_FP32_REFINE;
+    hipError_t e = plan->formulation == PANEL_HESS_SMITH
+                       ? launch_assemble_hs(v, plan->B, plan->max_ld, mixed, xy, alpha, chord, vinf,
+                                            static_cast<hipStream_t>(stream))
+                       : launch_assemble(v, plan->B, plan->max_cols, mixed, xy, alpha, chord, vinf,
+                                         static_cast<hipStream_t>(stream));
     return check_hip(e, "assembly launch");
 }
 
@@ -317,7 +371,8 @@ panel_status panel_factor_solve(const panel_plan *plan, void *ws, double refine_
         return fail(PANEL_EINVAL, "wave limit changed: call panel_workspace_init before factoring");
     WsView v = ws_view(ws, plan->layout);
     hipError_t e = launch_factor_solve(v, plan->B, plan->n_block, plan->max_n1_block, mixed, refine_tol,
-                                       max_iter, info, static_cast<hipStream_t>(stream));
+                                       max_iter, info, plan->tiling.persistent, plan->tiling.wg_waves,
+                                       static_cast<hipStream_t>(stream));
     return check_hip(e, "factor/solve launch");
 }
 
@@ -327,8 +382,9 @@ panel_status panel_forces(const panel_plan *plan, const void *ws, double *gamma,
     if ((gamma && !aligned8(gamma)) || (cp && !aligned8(cp)) || !aligned8(cl) || (cl_p && !aligned8(cl_p)))
         return fail(PANEL_EINVAL, "arrays must be 8-byte aligned");
     WsView v = ws_view(const_cast<void *>(ws), plan->layout);
-    hipError_t e = launch_forces(v, plan->B, plan->max_k, gamma, cp, cl, cl_p,
-                                 static_cast<hipStream_t>(stream));
+    hipError_t e = plan->formulation == PANEL_HESS_SMITH
+                       ? launch_forces_hs(v, plan->B, plan->max_k, gamma, cp, cl, cl_p, static_cast<hipStream_t>(stream))
+                       : launch_forces(v, plan->B, plan->max_k, gamma, cp, cl, cl_p, static_cast<hipStream_t>(stream));
     return check_hip(e, "forces launch");
 }
 
@@ -342,6 +398,8 @@ panel_status panel_adjoint(const panel_plan *plan, const void *ws, const double 
     if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(PANEL_EINVAL, "workspace must be 256-byte aligned");
     if (plan->order_stale)
         return fail(PANEL_EINVAL, "wave limit changed: call panel_workspace_init (and refactor) first");
+    if (plan->formulation != PANEL_STREAM_FUNCTION)
+        return fail(PANEL_EUNSUPPORTED, "the adjoint covers the stream-function formulation only");
     WsView v = ws_view(const_cast<void *>(ws), plan->layout);
     hipError_t e = launch_adjoint(v, plan->B, plan->n_block, plan->max_k, plan->precision == PANEL_FP32_REFINE,
                                   xy, dcl, dcp, dxy, info, static_cast<hipStream_t>(stream));
@@ -379,11 +437,15 @@ panel_status panel_solve_noalloc(const panel_plan *plan, const double *xy, const
     hipError_t e = hipMemcpyAsync(ws, plan->blob.data(), plan->blob.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return check_hip(e, "scratch metadata copy");
     WsView v = ws_view(ws, plan->layout);
-    e = launch_assemble(v, plan->B, plan->max_cols, mixed, xy, alpha, chord, vinf, s);
+    e = plan->formulation == PANEL_HESS_SMITH
+            ? launch_assemble_hs(v, plan->B, plan->max_ld, mixed, xy, alpha, chord, vinf, s)
+            : launch_assemble(v, plan->B, plan->max_cols, mixed, xy, alpha, chord, vinf, s);
     if (e != hipSuccess) return check_hip(e, "assembly launch");
-    e = launch_factor_solve(v, plan->B, plan->n_block, plan->max_n1_block, mixed, refine_tol, max_iter, info, s);
+    e = launch_factor_solve(v, plan->B, plan->n_block, plan->max_n1_block, mixed, refine_tol, max_iter, info,
+                            plan->tiling.persistent, plan->tiling.wg_waves, s);
     if (e != hipSuccess) return check_hip(e, "factor/solve launch");
-    e = launch_forces(v, plan->B, plan->max_k, gamma, cp, cl, cl_p, s);
+    e = plan->formulation == PANEL_HESS_SMITH ? launch_forces_hs(v, plan->B, plan->max_k, gamma, cp, cl, cl_p, s)
+                                              : launch_forces(v, plan->B, plan->max_k, gamma, cp, cl, cl_p, s);
     return check_hip(e, "forces launch");
 }
 

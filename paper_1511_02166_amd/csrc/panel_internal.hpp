@@ -34,7 +34,7 @@ struct PanelGeom {
 
 // Byte offsets of the workspace sections (all 256-byte aligned).
 struct WsLayout {
-    size_t meta, order, flag, chord, alpha, geom, a64, a32, x, piv, iters, total;
+    size_t meta, order, queue, flag, chord, alpha, geom, a64, a32, tg, x, piv, iters, total;
 };
 
 // Scalars copied with the metadata.
@@ -51,12 +51,15 @@ struct WsView {
     WsHeader *hdr;
     AirfoilMeta *meta;
     int32_t *order;     // airfoils by decreasing cost (LPT order)
+    int32_t *queue;     // work-queue counters of the persistent factorisation
+                        // (zero between launches; the last workgroup out resets them)
     int32_t *flag;      // per airfoil: 0 ok, -1 bad geometry (set by assembly)
     double *chord;      // per airfoil
     double *alpha;      // per angle
     PanelGeom *geom;    // per panel
     double *a64;        // FP64 systems (factored in place for PANEL_FP64)
     float *a32;         // FP32 systems (mixed path; factored in place)
+    double *tg;         // tangential-velocity influence matrices (Hess-Smith; same offsets as a64)
     double *x;          // solutions
     int32_t *piv;       // pivots (0-based row exchanged at each step)
     int32_t *iters;     // refinement sweeps per airfoil
@@ -68,12 +71,14 @@ inline __host__ __device__ WsView ws_view(void *ws, const WsLayout &l) {
     v.hdr = reinterpret_cast<WsHeader *>(b);
     v.meta = reinterpret_cast<AirfoilMeta *>(b + l.meta);
     v.order = reinterpret_cast<int32_t *>(b + l.order);
+    v.queue = reinterpret_cast<int32_t *>(b + l.queue);
     v.flag = reinterpret_cast<int32_t *>(b + l.flag);
     v.chord = reinterpret_cast<double *>(b + l.chord);
     v.alpha = reinterpret_cast<double *>(b + l.alpha);
     v.geom = reinterpret_cast<PanelGeom *>(b + l.geom);
     v.a64 = reinterpret_cast<double *>(b + l.a64);
     v.a32 = l.a32 ? reinterpret_cast<float *>(b + l.a32) : nullptr;
+    v.tg = l.tg ? reinterpret_cast<double *>(b + l.tg) : nullptr;
     v.x = reinterpret_cast<double *>(b + l.x);
     v.piv = reinterpret_cast<int32_t *>(b + l.piv);
     v.iters = reinterpret_cast<int32_t *>(b + l.iters);
@@ -94,15 +99,25 @@ hipError_t launch_assemble(const WsView &v, int32_t B, int32_t max_cols, int32_t
 // group in LPT order).
 constexpr int PANEL_WAVE_RMAX = 5;
 constexpr int PANEL_WAVE_MAX_N1 = 64 * PANEL_WAVE_RMAX;
+// persistent: one launch that pops both kinds of systems from the order
+// (and refines each FP32 solution right after its factorisation); used when
+// every workgroup-kernel system fits four wavefronts (n1 <= 768) and
+// wg_waves != 8.  wg_waves: 4 or 8 wavefronts per workgroup-kernel system,
+// 0 = eight when the batch has at most one airfoil per CU.
 hipError_t launch_factor_solve(const WsView &v, int32_t B, int32_t n_block, int32_t max_n1_block,
                                int32_t mixed, double tol, int32_t max_iter, int32_t *info,
-                               hipStream_t stream);
+                               int32_t persistent, int32_t wg_waves, hipStream_t stream);
 hipError_t launch_lu_wave(const WsView &v, int32_t first, int32_t count, int32_t mixed, int32_t *info,
                           hipStream_t stream);
 hipError_t launch_refine_wave(const WsView &v, int32_t first, int32_t count, int32_t *info, double tol,
                               int32_t max_iter, hipStream_t stream);
 hipError_t launch_forces(const WsView &v, int32_t B, int32_t max_k, double *gamma, double *cp,
                          double *cl, double *cl_p, hipStream_t stream);
+// Hess-Smith formulation (assemble_hs.hip): assembly + Kutta row, and forces.
+hipError_t launch_assemble_hs(const WsView &v, int32_t B, int32_t max_ld, int32_t mixed, const double *xy,
+                              const double *alpha, const double *chord, double vinf, hipStream_t stream);
+hipError_t launch_forces_hs(const WsView &v, int32_t B, int32_t max_k, double *gamma, double *cp, double *cl,
+                            double *cl_p, hipStream_t stream);
 hipError_t launch_math_eval(int32_t n, const double *x, const double *y, double *lg, double *at,
                             hipStream_t stream);
 // ka < 0: one pass with cl cotangents for all angles; ka >= 0: angle ka

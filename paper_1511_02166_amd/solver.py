@@ -5,6 +5,10 @@ all arithmetic happens in the library's HIP kernels.
 """
 from __future__ import annotations
 
+import hashlib
+import json
+import os
+
 import numpy as np
 import torch
 
@@ -17,6 +21,30 @@ def _aligned_workspace(nbytes: int, device) -> tuple[torch.Tensor, torch.Tensor]
     return raw, raw[off:off + nbytes]
 
 
+class TileTable:
+    """Measured tilings per batch layout (the autotuner's table), optionally
+    kept in a JSON file so that later runs with the same layout (a genetic
+    algorithm's generations) skip the search."""
+
+    def __init__(self, path: str | None = None):
+        self.path = path
+        self.entries = {}
+        if path and os.path.exists(path):
+            with open(path) as f:
+                self.entries = json.load(f)
+
+    def get(self, key):
+        return self.entries.get(key)
+
+    def put(self, key, entry):
+        self.entries[key] = entry
+        if self.path:
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.entries, f, indent=1)
+            os.replace(tmp, self.path)
+
+
 class PanelSolver:
     """One batch layout (node and angle offsets) with its workspace and outputs.
 
@@ -27,10 +55,13 @@ class PanelSolver:
     """
 
     def __init__(self, node_offsets, alpha_offsets, precision=B.PANEL_FP64, device="cuda",
-                 wave_limit=None):
+                 wave_limit=None, tiling=None):
         self.device = torch.device(device)
         self.plan = B.Plan(node_offsets, alpha_offsets, precision)
-        if wave_limit is not None:
+        if tiling is not None:
+            B.panel_plan_set_tiling(self.plan, *tiling)
+            wave_limit = tiling[0]
+        elif wave_limit is not None:
             B.panel_plan_set_wave_limit(self.plan, wave_limit)
         self.wave_limit = 320 if wave_limit is None else int(wave_limit)
         self.precision = int(precision)
@@ -59,28 +90,80 @@ class PanelSolver:
         B.panel_workspace_init(self.plan, self.ws)
         self.wave_limit = int(max_n1)
 
-    def autotune(self, xy, alpha, chord=None, vinf=1.0, refine_tol=1e-10, max_iter=10, candidates=(320, 0),
-                 reps=3):
-        """Measure the step (assembly -> factor/solve -> forces) on this batch
-        for each kernel choice and keep the fastest.
+    @property
+    def tiling(self) -> dict:
+        return B.panel_plan_get_tiling(self.plan)
 
-        The one-wavefront kernels win when there are more systems than SIMDs;
-        with few systems (or for the refinement of small batches) a
-        workgroup per system uses the chip better.  Returns {limit: ms}."""
+    def set_tiling(self, wave_max_n1: int, persistent: int = 1, wg_waves: int = 0):
+        """Kernel mapping of the factorisation (panel_tiling in include/panel.h)."""
+        B.panel_plan_set_tiling(self.plan, wave_max_n1, persistent, wg_waves)
+        B.panel_workspace_init(self.plan, self.ws)
+        self.wave_limit = int(wave_max_n1)
+
+    def tiling_candidates(self):
+        """Distinct tilings for this batch: wave limits that split the systems
+        differently, one launch or one per kernel family, and four or eight
+        wavefronts per workgroup-factored system where some exist."""
+        n1 = np.asarray(self.plan.n_panels) + 1
+        out, seen = [], set()
+        for wl in (320, 256, 192, 128, 0):
+            big = n1 > wl
+            nb = int(big.sum())
+            key_part = tuple(np.flatnonzero(big)) if 0 < nb < len(n1) else nb
+            wgs = (0,) if nb == 0 else ((8,) if int(n1.max()) > 768 else (4, 8))
+            for pers in (1, 0):
+                for wg in wgs:
+                    # one launch applies only where the workgroup systems fit four wavefronts
+                    eff_pers = pers if (nb == 0 or wg == 4) else 0
+                    key = (key_part, eff_pers, wg)
+                    if key in seen:
+                        continue
+                    seen.add(key)
+                    out.append((wl, eff_pers, wg))
+        return out
+
+    def shape_key(self) -> str:
+        """Identifies the batch layout (precision, panel and angle counts)."""
+        h = hashlib.sha256()
+        h.update(np.asarray([self.precision], dtype=np.int64).tobytes())
+        h.update(np.ascontiguousarray(self.plan.node_offsets, dtype=np.int32).tobytes())
+        h.update(np.ascontiguousarray(self.plan.alpha_offsets, dtype=np.int32).tobytes())
+        return h.hexdigest()[:24]
+
+    def autotune(self, xy, alpha, chord=None, vinf=1.0, refine_tol=1e-10, max_iter=10, reps=3,
+                 table: "TileTable | None" = None, candidates=None):
+        """Time the step (assembly -> factor/solve -> forces) on this batch for
+        every candidate tiling and keep the fastest.
+
+        With a ``table`` whose entry for this batch layout exists, that entry
+        is applied without timing; otherwise the measured result is stored in
+        it.  Returns {(wave_max_n1, persistent, wg_waves): ms}."""
+        key = self.shape_key()
+        if table is not None:
+            hit = table.get(key)
+            if hit is not None:
+                self.set_tiling(*hit["tiling"])
+                return {tuple(k): v for k, v in hit["times"]}
         times = {}
-        for lim in candidates:
-            self.set_wave_limit(lim)
+        for cand in (candidates or self.tiling_candidates()):
+            self.set_tiling(*cand)
             self.step(xy, alpha, chord, vinf, refine_tol, max_iter)
             torch.cuda.synchronize(self.device)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
+            ms = []
             for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
                 self.step(xy, alpha, chord, vinf, refine_tol, max_iter)
-            e1.record()
-            torch.cuda.synchronize(self.device)
-            times[lim] = e0.elapsed_time(e1) / reps
-        self.set_wave_limit(min(times, key=times.get))
+                e1.record()
+                torch.cuda.synchronize(self.device)
+                ms.append(e0.elapsed_time(e1))
+            times[tuple(cand)] = float(np.median(ms))
+        best = min(times, key=times.get)
+        self.set_tiling(*best)
+        if table is not None:
+            table.put(key, dict(tiling=list(best), times=[[list(k), v] for k, v in times.items()],
+                                B=self.B, precision=self.precision))
         return times
 
     # -- steps ---------------------------------------------------------------

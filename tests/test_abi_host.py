@@ -147,3 +147,22 @@ def test_noalloc_entry_refuses_oversized_plans_before_hip(lib):
                                    None, None, fake, None, None) == P._binding.PANEL_EINVAL
     assert b"static scratch" in lib.panel_last_error()
     lib.panel_plan_destroy(h)
+
+
+def test_tiling_defaults_and_validation(lib):
+    import paper_1511_02166_amd as P
+    from paper_1511_02166_amd._binding import panel_tiling
+    EINVAL = P._binding.PANEL_EINVAL
+    st, h = _plan(lib, [0, 129, 500], [0, 1, 2])
+    t = panel_tiling()
+    assert lib.panel_plan_get_tiling(h, C.byref(t)) == 0
+    assert t.as_dict() == dict(wave_max_n1=320, persistent=0, wg_waves=0)
+    for bad in ((321, 1, 0), (-1, 1, 0), (320, 2, 0), (320, 1, 6)):
+        assert lib.panel_plan_set_tiling(h, C.byref(panel_tiling(*bad))) == EINVAL, bad
+    assert lib.panel_plan_set_tiling(h, C.byref(panel_tiling(192, 0, 8))) == 0
+    assert lib.panel_plan_get_tiling(h, C.byref(t)) == 0 and t.as_dict() == dict(wave_max_n1=192, persistent=0,
+                                                                                   wg_waves=8)
+    # a new wave limit needs the workspace re-initialised before factoring
+    fake = C.c_void_p(0x100000)
+    assert lib.panel_factor_solve(h, fake, C.c_double(1e-10), 10, fake, None) == EINVAL
+    lib.panel_plan_destroy(h)

@@ -62,6 +62,30 @@ def _ok(e, tol):
     return all(e[k] < tol for k in ("cl", "cl_p", "cp", "gamma"))
 
 
+def _assert_parity(got, ref, w, xy_flat, tol):
+    """Per airfoil and quantity: error < tol, or, where the error is larger,
+    < FLOOR_FACTOR x the floor measured on that airfoil's system (needed for
+    the larger panel counts, whose FP64 floor reaches ~1e-10)."""
+    noff, aoff = w.node_offsets(), w.alpha_offsets()
+    Ns, Ks = np.diff(noff) - 1, np.diff(aoff)
+    so = np.concatenate([[0], np.cumsum(Ns * Ks)])
+    worst = 0.0
+    for b in range(w.B):
+        sa, ss = slice(aoff[b], aoff[b + 1]), slice(so[b], so[b + 1])
+        e = dict(cl=np.max(np.abs(got["cl"][sa] - ref["cl"][sa]) / np.maximum(1.0, np.abs(ref["cl"][sa]))),
+                 cl_p=np.max(np.abs(got["cl_p"][sa] - ref["cl_p"][sa]) / np.maximum(1.0, np.abs(ref["cl_p"][sa]))),
+                 cp=np.max(np.abs(got["cp"][ss] - ref["cp"][ss])) / max(1.0, np.max(np.abs(ref["cp"][ss]))),
+                 gamma=np.max(np.abs(got["gamma"][ss] - ref["gamma"][ss])) / max(1.0, np.max(np.abs(ref["gamma"][ss]))))
+        worst = max(worst, max(e.values()))
+        if _ok(e, tol):
+            continue
+        fl = measured_floor(xy_flat[2 * noff[b]:2 * noff[b + 1]], w.alpha[b])
+        _say(f"  airfoil {b} N={Ns[b]}: " + " ".join(f"{q} {e[q]:.1e}/{fl[q]:.0e}" for q in e) + " (error/floor)")
+        for q in e:
+            assert e[q] < max(tol, FLOOR_FACTOR * fl[q]), (b, q, e[q], fl[q])
+    return worst
+
+
 def _errors(gpu, ref, w):
     """Per-airfoil worst relative errors of Cl and Cp (G10 reading)."""
     noff, aoff = w.node_offsets(), w.alpha_offsets()
@@ -78,12 +102,13 @@ def _errors(gpu, ref, w):
     return dict(cl=e_cl.max(), cl_p=e_clp.max(), cp=e_cp.max(), gamma=e_g.max())
 
 
-def _run(w, precision, xy_flat=None, refine_tol=1e-10, max_iter=10, wave_limit=None, chord=None, vinf=1.0):
+def _run(w, precision, xy_flat=None, refine_tol=1e-10, max_iter=10, wave_limit=None, chord=None, vinf=1.0,
+         tiling=None):
     """GPU solve; returns (solver, outputs, the node array the GPU used)."""
     import paper_1511_02166_amd as P
     torch = _torch()
     xy, alpha = _gpu_inputs(w, xy_flat)
-    s = P.PanelSolver(w.node_offsets(), w.alpha_offsets(), precision, wave_limit=wave_limit)
+    s = P.PanelSolver(w.node_offsets(), w.alpha_offsets(), precision, wave_limit=wave_limit, tiling=tiling)
     ch = None if chord is None else torch.as_tensor(np.asarray(chord, dtype=np.float64), device="cuda")
     out = s.solve(xy, alpha, chord=ch, vinf=vinf, refine_tol=refine_tol, max_iter=max_iter)
     torch.cuda.synchronize()
@@ -204,13 +229,13 @@ def test_fp32_refined_pipeline_matches_oracle(name, B, wave_limit):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("wave_limit", [None, 0])
-def test_uneven_batch_matches_oracle(precision, wave_limit):
+@pytest.mark.parametrize("wave_limit,persistent", [(320, 1), (320, 0), (0, 1), (0, 0)])
+def test_uneven_batch_matches_oracle(precision, wave_limit, persistent):
     # K = 1..4 per airfoil: odd counts exercise the refinement's single
-    # right-hand-side tail in both kernel families
-    _say(f"uneven batch parity, precision={precision}, wave_limit={wave_limit}")
+    # right-hand-side tail in both kernel families, in one launch or separately
+    _say(f"uneven batch parity, precision={precision}, wave_limit={wave_limit}, persistent={persistent}")
     w = synth.random_workload(11, 40, n_choices=(4, 6, 16, 30, 64, 96, 130, 250, 256, 300), k_max=4)
-    s, got = _run(w, precision, wave_limit=wave_limit)
+    s, got = _run(w, precision, tiling=(wave_limit, persistent, 4))
     ref = _oracle(w, got["xy"])
     assert np.all(got["info"] == 0)
     e = _errors(got, ref, w)
@@ -398,24 +423,65 @@ def test_lu_factors_reproduce_matrix(precision, sizes, wave_limit):
         assert ry < tol * n, (N, ry)
 
 
-def test_autotune_picks_a_kernel_and_keeps_results():
-    # the measured kernel choice changes which kernels run, not the answer
+def test_autotune_picks_a_tiling_and_keeps_results(tmp_path):
+    # the measured tiling changes which kernels run, not the answer; the
+    # table file makes the next search for the same layout a lookup
     import paper_1511_02166_amd as P
     torch = _torch()
-    w = synth.workload("ga2048", B=128)
-    _say("autotune of the kernel choice, 128 airfoils, both precisions")
+    w = synth.random_workload(43, 96, n_choices=(64, 128, 256, 300, 400, 510), k_max=2)
+    _say("autotune of the tiling, 96 mixed sections (N 64..510), both precisions")
     xy, alpha = _gpu_inputs(w)
     ref = _oracle(w, xy.cpu().numpy())
+    table = P.TileTable(str(tmp_path / "tiles.json"))
     for prec, tol in ((P.PANEL_FP64, TOL64), (P.PANEL_FP32_REFINE, TOL32R)):
         s = P.PanelSolver(w.node_offsets(), w.alpha_offsets(), prec)
-        times = s.autotune(xy, alpha)
-        _say(f"  precision {prec}: {times} -> wave limit {s.wave_limit}")
-        assert set(times) == {320, 0} and s.wave_limit == min(times, key=times.get)
+        cands = s.tiling_candidates()
+        times = s.autotune(xy, alpha, table=table)
+        best = min(times, key=times.get)
+        _say(f"  precision {prec}: {len(cands)} candidates, best {best} at {times[best]:.3f} ms")
+        assert set(times) == set(cands) and len(cands) > 4
+        t = s.tiling
+        assert (t["wave_max_n1"], t["persistent"], t["wg_waves"]) == best
         out = s.solve(xy, alpha)
         torch.cuda.synchronize()
         got = {k: v.cpu().numpy() for k, v in out.items()}
-        e = _errors(got, ref, w)
-        assert np.all(got["info"] == 0) and _ok(e, tol), e
+        assert np.all(got["info"] == 0)
+        _assert_parity(got, ref, w, xy.cpu().numpy(), tol)
+        # a second solver with the same layout takes the stored entry
+        s2 = P.PanelSolver(w.node_offsets(), w.alpha_offsets(), prec)
+        assert s2.autotune(xy, alpha, table=P.TileTable(str(tmp_path / "tiles.json"))) == times
+        t2 = s2.tiling
+        assert (t2["wave_max_n1"], t2["persistent"], t2["wg_waves"]) == best
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_persistent_launch_matches_separate_launches(precision):
+    # The persistent kernel runs the same per-airfoil arithmetic as the
+    # separate kernels, only scheduled from one queue: identical results,
+    # also on a second and third call (its queue counters reset themselves)
+    # and with the wave limit moved so that the workgroup path takes a share.
+    import paper_1511_02166_amd as P
+    torch = _torch()
+    w = synth.random_workload(47, 70, n_choices=(4, 30, 64, 128, 250, 300, 318, 320, 400, 510, 640, 766), k_max=3)
+    _say(f"persistent vs separate launches, precision={precision}")
+    xy, alpha = _gpu_inputs(w)
+    ref = _oracle(w, xy.cpu().numpy())
+    tol = TOL64 if precision == 0 else TOL32R
+    for wl in (320, 192):
+        outs = []
+        for tiling in ((wl, 1, 4), (wl, 0, 4), (wl, 0, 8)):
+            s = P.PanelSolver(w.node_offsets(), w.alpha_offsets(), precision, tiling=tiling)
+            for rep in range(3):
+                out = s.solve(xy, alpha)
+                torch.cuda.synchronize()
+                got = {k: v.cpu().numpy() for k, v in out.items()}
+                assert np.all(got["info"] == 0), (tiling, rep, got["info"])
+                worst = _assert_parity(got, ref, w, xy.cpu().numpy(), tol)
+            outs.append(got)
+            _say(f"  tiling {tiling}: worst error {worst:.2e}")
+        # four-wavefront workgroups, one launch or two: the same arithmetic
+        for k in ("gamma", "cp", "cl", "cl_p"):
+            assert np.array_equal(outs[0][k], outs[1][k]), (wl, k)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
