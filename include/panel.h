@@ -160,10 +160,12 @@ panel_status panel_plan_get_tiling(const panel_plan *plan, panel_tiling *tiling)
 panel_status panel_workspace_size(const panel_plan *plan, size_t *bytes);
 
 /* Where airfoil b's data sit inside a workspace (for inspection and tests):
- * h_desc receives 8 int64 values: byte offsets of the FP64 augmented system
+ * h_desc receives 9 int64 values: byte offsets of the FP64 augmented system
  * (column-major, ld rows, n1 + K columns), of the FP32 system (-1 unless
  * PANEL_FP32_REFINE), of the K solutions, of the n1 int32 pivots, then n1,
- * ld, K, and the byte offset of the int32 refinement-sweep counter.        */
+ * ld, K, the byte offset of the int32 refinement-sweep counter, and of the
+ * tangential-velocity matrix (column-major, ld rows, n1 columns; -1 unless
+ * PANEL_HESS_SMITH).                                                        */
 panel_status panel_workspace_layout(const panel_plan *plan, int32_t b, int64_t *h_desc);
 
 /* Write the plan's per-airfoil metadata into the workspace (one host-to-

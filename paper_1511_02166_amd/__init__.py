@@ -12,6 +12,8 @@ from __future__ import annotations
 from ._binding import (  # noqa: F401
     PANEL_FP32_REFINE,
     PANEL_FP64,
+    PANEL_HESS_SMITH,
+    PANEL_STREAM_FUNCTION,
     PANEL_KMAX,
     PANEL_NMAX,
     PANEL_NMIN,
@@ -31,6 +33,7 @@ from ._binding import (  # noqa: F401
     panel_plan_create,
     panel_plan_destroy,
     panel_plan_get_tiling,
+    panel_plan_set_formulation,
     panel_plan_set_tiling,
     panel_plan_set_wave_limit,
     panel_solve_noalloc,
@@ -42,10 +45,10 @@ from ._binding import (  # noqa: F401
 from .solver import PanelSolver, TileTable, naca_cl, panel_cl, panel_cl_cp  # noqa: F401
 
 __all__ = [
-    "PANEL_FP64", "PANEL_FP32_REFINE", "PANEL_NMAX", "PANEL_NMIN", "PANEL_KMAX",
+    "PANEL_FP64", "PANEL_FP32_REFINE", "PANEL_STREAM_FUNCTION", "PANEL_HESS_SMITH", "PANEL_NMAX", "PANEL_NMIN", "PANEL_KMAX",
     "PanelError", "Plan", "PanelSolver", "TileTable", "panel_cl", "panel_cl_cp", "naca_cl",
     "panel_plan_create", "panel_plan_destroy", "panel_plan_set_wave_limit", "panel_plan_set_tiling",
-    "panel_plan_get_tiling", "panel_workspace_size", "panel_workspace_init", "panel_workspace_layout",
+    "panel_plan_get_tiling", "panel_plan_set_formulation", "panel_workspace_size", "panel_workspace_init", "panel_workspace_layout",
     "panel_assemble", "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
     "panel_naca4_vjp", "panel_math_eval", "panel_solve_noalloc", "PANEL_NOALLOC_MAX_BYTES", "panel_status_str", "panel_last_error", "load_library", "lib_path",
 ]

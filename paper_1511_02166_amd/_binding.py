@@ -11,6 +11,7 @@ _LIB_PATH = os.path.join(HERE, "libpanel.so")
 
 PANEL_OK, PANEL_EINVAL, PANEL_ENOMEM, PANEL_EHIP, PANEL_EUNSUPPORTED = range(5)
 PANEL_FP64, PANEL_FP32_REFINE = 0, 1
+PANEL_STREAM_FUNCTION, PANEL_HESS_SMITH = 0, 1
 PANEL_NMAX, PANEL_NMIN, PANEL_KMAX = 1024, 4, 16
 PANEL_NOALLOC_MAX_BYTES = 256 << 20
 
@@ -50,6 +51,7 @@ def load_library():
     L.panel_plan_destroy.restype = None
     L.panel_plan_set_wave_limit.argtypes = [vp, i32]
     L.panel_plan_set_tiling.argtypes = [vp, C.POINTER(panel_tiling)]
+    L.panel_plan_set_formulation.argtypes = [vp, i32]
     L.panel_plan_get_tiling.argtypes = [vp, C.POINTER(panel_tiling)]
     L.panel_workspace_size.argtypes = [vp, C.POINTER(sz)]
     L.panel_workspace_init.argtypes = [vp, vp, vp]
@@ -67,6 +69,7 @@ def load_library():
     L.panel_last_error.argtypes = []
     L.panel_last_error.restype = C.c_char_p
     for name in ("panel_plan_create", "panel_plan_set_wave_limit", "panel_plan_set_tiling", "panel_plan_get_tiling",
+                 "panel_plan_set_formulation",
                  "panel_workspace_size", "panel_workspace_init",
                  "panel_workspace_layout", "panel_assemble",
                  "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
@@ -117,7 +120,7 @@ def _stream(stream):
 class Plan:
     """Owner of a ``panel_plan*`` (host metadata for one batch layout)."""
 
-    def __init__(self, node_offsets, alpha_offsets, precision=PANEL_FP64):
+    def __init__(self, node_offsets, alpha_offsets, precision=PANEL_FP64, formulation=PANEL_STREAM_FUNCTION):
         L = load_library()
         no = np.ascontiguousarray(node_offsets, dtype=np.int32)
         ao = np.ascontiguousarray(alpha_offsets, dtype=np.int32)
@@ -131,6 +134,9 @@ class Plan:
         _check(L.panel_plan_create(self.B, no.ctypes.data_as(C.c_void_p), ao.ctypes.data_as(C.c_void_p),
                                    self.precision, C.byref(h)))
         self._h = h
+        self.formulation = int(formulation)
+        if self.formulation != PANEL_STREAM_FUNCTION:
+            _check(L.panel_plan_set_formulation(h, self.formulation))
         self.n_nodes = int(no[-1])
         self.n_alpha = int(ao[-1])
         n = np.diff(no).astype(np.int64) - 1
@@ -149,10 +155,10 @@ class Plan:
         return int(out.value)
 
     def layout(self, b: int) -> dict:
-        d = np.zeros(8, dtype=np.int64)
+        d = np.zeros(9, dtype=np.int64)
         _check(load_library().panel_workspace_layout(self._h, int(b), d.ctypes.data_as(C.c_void_p)))
         return dict(a64=int(d[0]), a32=int(d[1]), x=int(d[2]), piv=int(d[3]), n1=int(d[4]),
-                    ld=int(d[5]), K=int(d[6]), iters=int(d[7]))
+                    ld=int(d[5]), K=int(d[6]), iters=int(d[7]), tg=int(d[8]))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -165,6 +171,12 @@ class Plan:
 
 def panel_plan_create(node_offsets, alpha_offsets, precision=PANEL_FP64) -> Plan:
     return Plan(node_offsets, alpha_offsets, precision)
+
+
+def panel_plan_set_formulation(plan: Plan, formulation: int):
+    """PANEL_STREAM_FUNCTION or PANEL_HESS_SMITH (before sizing the workspace)."""
+    _check(load_library().panel_plan_set_formulation(plan.handle, int(formulation)))
+    plan.formulation = int(formulation)
 
 
 def panel_plan_destroy(plan: Plan):

@@ -318,6 +318,7 @@ panel_status panel_workspace_layout(const panel_plan *plan, int32_t b, int64_t *
     h_desc[5] = m.ld;
     h_desc[6] = m.K;
     h_desc[7] = int64_t(l.iters + sizeof(int32_t) * b);
+    h_desc[8] = l.tg ? int64_t(l.tg + sizeof(double) * m.a_off) : -1;
     return ok();
 }
 

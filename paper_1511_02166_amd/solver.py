@@ -55,9 +55,10 @@ class PanelSolver:
     """
 
     def __init__(self, node_offsets, alpha_offsets, precision=B.PANEL_FP64, device="cuda",
-                 wave_limit=None, tiling=None):
+                 wave_limit=None, tiling=None, formulation=B.PANEL_STREAM_FUNCTION):
         self.device = torch.device(device)
-        self.plan = B.Plan(node_offsets, alpha_offsets, precision)
+        self.plan = B.Plan(node_offsets, alpha_offsets, precision, formulation)
+        self.formulation = int(formulation)
         if tiling is not None:
             B.panel_plan_set_tiling(self.plan, *tiling)
             wave_limit = tiling[0]
@@ -221,6 +222,15 @@ class PanelSolver:
             t = self.ws[d["a32"]:d["a32"] + 4 * ld * (n1 + K)].view(torch.float32)
         cols = t.cpu().numpy().reshape(n1 + K, ld)[:, :n1]
         return cols[:n1].T.copy(), cols[n1:].copy()
+
+    def tangential(self, b: int) -> np.ndarray:
+        """Hess-Smith: airfoil b's tangential-velocity influence matrix [N, N+1]."""
+        if self.formulation != B.PANEL_HESS_SMITH:
+            raise ValueError("only the Hess-Smith formulation keeps a tangential matrix")
+        d = self.plan.layout(b)
+        n1, ld = d["n1"], d["ld"]
+        t = self.ws[d["tg"]:d["tg"] + 8 * ld * n1].view(torch.float64)
+        return t.cpu().numpy().reshape(n1, ld)[:, :n1 - 1].T.copy()
 
     def pivots(self, b: int) -> np.ndarray:
         d = self.plan.layout(b)

@@ -123,10 +123,10 @@ def test_entry_points_reject_bad_arguments_before_hip(lib):
 def test_layout_and_status_strings(lib):
     import paper_1511_02166_amd as P
     st, h = _plan(lib, [0, 257, 514], [0, 1, 5])
-    d = (C.c_int64 * 8)()
+    d = (C.c_int64 * 9)()
     assert lib.panel_workspace_layout(h, 1, d) == 0
     assert d[4] == 257 and d[5] == 288 and d[6] == 4
-    assert d[0] % 128 == 0
+    assert d[0] % 128 == 0 and d[8] == -1
     assert lib.panel_workspace_layout(h, 2, d) == P._binding.PANEL_EINVAL
     lib.panel_plan_destroy(h)
     for s in range(5):
@@ -165,4 +165,23 @@ def test_tiling_defaults_and_validation(lib):
     # a new wave limit needs the workspace re-initialised before factoring
     fake = C.c_void_p(0x100000)
     assert lib.panel_factor_solve(h, fake, C.c_double(1e-10), 10, fake, None) == EINVAL
+    lib.panel_plan_destroy(h)
+
+
+def test_formulation_switch_and_workspace(lib):
+    # Hess-Smith keeps the tangential-velocity matrix: one more system-sized
+    # section; unknown formulations are refused; its adjoint is unsupported
+    import paper_1511_02166_amd as P
+    st, h = _plan(lib, [0, 257, 514], [0, 1, 3])
+    s0 = C.c_size_t()
+    assert lib.panel_workspace_size(h, C.byref(s0)) == 0
+    assert lib.panel_plan_set_formulation(h, 7) == P._binding.PANEL_EINVAL
+    assert lib.panel_plan_set_formulation(h, P.PANEL_HESS_SMITH) == 0
+    s1 = C.c_size_t()
+    assert lib.panel_workspace_size(h, C.byref(s1)) == 0
+    assert s1.value - s0.value > 0.99 * 8 * 288 * (258 + 260)   # one more system-sized section
+    d = (C.c_int64 * 9)()
+    assert lib.panel_workspace_layout(h, 1, d) == 0 and d[8] > d[0]
+    fake = C.c_void_p(0x100000)
+    assert lib.panel_adjoint(h, fake, fake, fake, None, fake, None, None) == P._binding.PANEL_EUNSUPPORTED
     lib.panel_plan_destroy(h)
