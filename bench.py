@@ -45,7 +45,7 @@ ASM_FLOPS_PER_ENTRY = 118.0
 # batch, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's
 # readings (x2.0 and x1.0).  Valid only for the kernel source it was taken
 # on, which is identified by the SHA-256 prefix of that source file.
-LU_TRAFFIC = {}
+LU_TRAFFIC = {("lu_wave_impl.hpp", "efb29edbf3f9df7f"): 10_221_091_922}   # one wavefront per airfoil
 
 # Host threads for the oracle: the box assigns 16 host cores to each GPU.
 CPU_SHARE = 16
@@ -268,7 +268,7 @@ def main():
     traffic = None
     if dom == "lu_solve_f64" and a.workload == "ga2048" and a.batch is None and a.wave_limit is None:
         import hashlib
-        src = "lu_wave.hip"
+        src = "lu_wave_impl.hpp"   # the one-wavefront factorisation's source
         with open(os.path.join(os.path.dirname(P.__file__), "csrc", src), "rb") as f:
             traffic = LU_TRAFFIC.get((src, hashlib.sha256(f.read()).hexdigest()[:16]))
     roof = {"kernel": dom, **{k: kern[dom][k] for k in ("bound", "achieved", "peak", "unit", "frac")},

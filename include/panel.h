@@ -191,9 +191,11 @@ panel_status panel_assemble(const panel_plan *plan, const double *xy, const doub
  * sides (Sec. 3: LU, (2/3)n^3 operations).  With PANEL_FP32_REFINE the
  * factorisation is in FP32 and the solution is refined: r = b - A x in
  * FP64, correction from the FP32 factors, x += correction, until
- * ||correction||_inf <= refine_tol * ||x||_inf, or until the residual sits at
- * the FP64 backward-error floor ||r||_inf <= sqrt(n) eps ||A||_inf ||x||_inf
- * (no sweep can improve x further), or max_iter sweeps (info -2).
+ * ||correction||_inf <= refine_tol * ||x||_inf, or the correction that the
+ * last two predict for the next sweep under linear convergence at a rate
+ * below 1/2, ||d_k||^2 / (||d_{k-1}|| - ||d_k||), is, or until the residual
+ * sits at the FP64 backward-error floor ||r||_inf <= sqrt(n) eps ||A||_inf
+ * ||x||_inf (no sweep can improve x further), or max_iter sweeps (info -2).
  * max_iter = 0 disables refinement and reports -2 (result unverified).
  *   refine_tol  > 0 (ignored for PANEL_FP64)
  *   max_iter    0..100 (ignored for PANEL_FP64)

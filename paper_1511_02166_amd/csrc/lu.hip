@@ -679,10 +679,12 @@ __device__ __forceinline__ void wg_refine(const WsView &v, int b, int32_t *__res
         __syncthreads();
         bool conv[KG];
         int sweeps[KG];
+        double dprev[KG];
 #pragma unroll
         for (int kk = 0; kk < KG; ++kk) {
             conv[kk] = kk >= kn;
             sweeps[kk] = 0;
+            dprev[kk] = -1.0;
         }
         for (int it = 0; it < max_iter; ++it) {
             bool all = true;
@@ -749,7 +751,8 @@ __device__ __forceinline__ void wg_refine(const WsView &v, int b, int32_t *__res
                 }
                 bmax3(dmax, xn, unused);
                 ++sweeps[kk];
-                conv[kk] = dmax <= tol * xn;
+                conv[kk] = wv::refined_enough(dmax, dprev[kk], xn, tol);
+                dprev[kk] = dmax;
             }
         }
 #pragma unroll

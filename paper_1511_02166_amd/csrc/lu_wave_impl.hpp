@@ -64,7 +64,7 @@ constexpr int WSP = 64;   // super-panel width (rank of the trailing update)
 // as fit in the register budget without spilling)
 template <typename T> struct Wct;
 template <> struct Wct<double> { static constexpr int v = 32; };
-template <> struct Wct<float> { static constexpr int v = 48; };
+template <> struct Wct<float> { static constexpr int v = 64; };
 constexpr int WNB = 16;   // pivot panel width
 
 typedef double d4w_t __attribute__((ext_vector_type(4)));
@@ -714,6 +714,17 @@ __device__ __forceinline__ void wave_trsv_lower_unit(const T *L, int ld, int n, 
     }
 }
 
+// Stop rule of the refinement after a correction of size d (inf-norm), the
+// previous one dprev (< 0 if none) and the corrected solution's size xn:
+// the correction itself is below tol xn, or, converging linearly at the
+// observed rate r = d / dprev < 1/2, the correction still to come is:
+// r d / (1 - r) = d^2 / (dprev - d) <= tol xn.  The second test saves the
+// sweep whose only purpose would be to confirm a correction far below tol.
+__device__ __forceinline__ bool refined_enough(double d, double dprev, double xn, double tol) {
+    if (d <= tol * xn) return true;
+    return dprev > 0.0 && d <= 0.5 * dprev && d * d <= tol * xn * (dprev - d);
+}
+
 // Largest value over the wavefront of three per-lane values.
 __device__ __forceinline__ void wave_max3(double &a, double &b, double &c) {
     a = wave_max(a);
@@ -775,6 +786,7 @@ __device__ __forceinline__ void wave_refine(const WsView &v, int b, int32_t *__r
         wave_sync();
         bool conv = false;
         int sweeps = 0;
+        double dprev = -1.0;   // size of the previous correction
         for (int it = 0; it < max_iter && !conv; ++it) {
             // residual, lane owns rows lane + 64 q
             double rs[RM], ra[RM];
@@ -842,7 +854,8 @@ __device__ __forceinline__ void wave_refine(const WsView &v, int b, int32_t *__r
             wave_max3(dmax, xn, unused);
             wave_sync();
             ++sweeps;
-            conv = dmax <= tol * xn;
+            conv = refined_enough(dmax, dprev, xn, tol);
+            dprev = dmax;
         }
         if (!conv) failed = true;
         worst = max(worst, sweeps);
