@@ -26,6 +26,10 @@ Parity status per function (see the pins under ``tests/``):
                         cylinder, Joukowski circulation, symmetric sections,
                         invariances, convergence to the stream-function
                         scheme's limit)
+  oracle_thwaites*      viscous correction (panel_oracle_bl.c): pinned
+                        (stagnation flow exact, power-law edge flows at second
+                        order, the circular cylinder's closed-form drag and
+                        separation angle, symmetry, Reynolds scaling)
 """
 from __future__ import annotations
 
@@ -37,7 +41,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = [os.path.join(_HERE, "panel_oracle.c"), os.path.join(_HERE, "panel_oracle_grad.c"),
-        os.path.join(_HERE, "panel_oracle_hs.c")]
+        os.path.join(_HERE, "panel_oracle_hs.c"), os.path.join(_HERE, "panel_oracle_bl.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -113,6 +117,11 @@ def lib():
         L.oracle_hs_solve_batch.argtypes = [C.c_int, _ip, _dp, _ip, _dp, C.c_void_p, C.c_double,
                                             _dp, _dp, _dp, _dp, _ip, C.c_int]
         L.oracle_hs_solve_batch.restype = C.c_int
+        L.oracle_thwaites_surface.argtypes = [C.c_int, _dp, _dp, C.c_double, _dp, _dp]
+        L.oracle_thwaites_surface.restype = C.c_int
+        L.oracle_thwaites.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp, _dp, C.c_double, C.c_double,
+                                      C.c_double, _dp, _dp, _ip]
+        L.oracle_thwaites.restype = None
         _lib = L
     return _lib
 
@@ -257,6 +266,32 @@ def hs_assemble(xy, alpha, vinf=1.0):
     Mt = np.zeros((N + 1) * (N + 1))
     lib().oracle_hs_assemble(N, xy, K, alpha, float(vinf), M, R, Mt)
     return M.reshape(N + 1, N + 1), R.reshape(K, N + 1), Mt.reshape(N + 1, N + 1)[:N]
+
+
+def thwaites_surface(ds, U, nu):
+    """One boundary-layer surface: (theta, lambda, index of the first
+    separated station or len(U))."""
+    ds, U = _f64(ds), _f64(U)
+    th = np.zeros(U.size)
+    lm = np.zeros(U.size)
+    sep = lib().oracle_thwaites_surface(int(U.size), ds, U, float(nu), th, lm)
+    return th, lm, int(sep)
+
+
+def thwaites(xy, alpha, u, cl, re, vinf=1.0, chord=1.0):
+    """Viscous correction of one airfoil from its surface speeds u [K, N] and
+    lift cl [K]: dict(cd[K], ld[K], sep[K, 2]) (separation panel of the upper
+    and lower layer, -1 if attached to the trailing edge)."""
+    xy = _f64(xy).reshape(-1)
+    N = xy.size // 2 - 1
+    alpha = _f64(np.atleast_1d(alpha))
+    K = alpha.size
+    cd = np.zeros(K)
+    ld = np.zeros(K)
+    sep = np.zeros(2 * K, dtype=np.int32)
+    lib().oracle_thwaites(N, xy, K, alpha, _f64(u).reshape(-1), _f64(np.atleast_1d(cl)), float(vinf),
+                          float(chord), float(re), cd, ld, sep)
+    return dict(cd=cd, ld=ld, sep=sep.reshape(K, 2))
 
 
 def cl_gradient(xy, alpha, vinf=1.0, chord=1.0, with_alpha=False):
