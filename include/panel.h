@@ -214,6 +214,28 @@ panel_status panel_factor_solve(const panel_plan *plan, void *ws, double refine_
 panel_status panel_forces(const panel_plan *plan, const void *ws, double *gamma, double *cp,
                           double *cl, double *cl_p, void *stream);
 
+/* Viscous correction (Sec. 2: the inviscid solution gives no drag, so a
+ * laminar boundary-layer method, Thwaites', corrects it; the genetic
+ * algorithm's fitness is the lift-to-drag ratio).  On the surface speed of
+ * each airfoil and angle: from the stagnation point (between the first pair
+ * of panel midpoints with gamma_j < 0 <= gamma_{j+1}) along both surfaces,
+ * theta^2 = 0.45 nu U^-6 int U^5 ds (U = |gamma| piecewise linear in the arc
+ * length), lambda = theta^2 U' / nu, laminar separation at the first station
+ * with lambda < -0.09, and up to it the wall shear of Thwaites' correlation
+ * integrated along the free stream:
+ *   cd [alpha_offsets[b] + k]  skin-friction drag / ((1/2) rho vinf^2 c_b),
+ *                              nu = vinf c_b / re
+ *   ld [.]                     cl / cd
+ *   sep[2 (alpha_offsets[b] + k) + {0, 1}]  panel where the upper / lower
+ *                              layer separates, -1 if it reaches the
+ *                              trailing edge, -2 (cd, ld NaN) if no
+ *                              stagnation point is found or info != 0
+ *   gamma, cl  the outputs of panel_forces for this workspace (the layer is
+ *              run on whatever they hold)
+ *   re         chord Reynolds number, finite and > 0                      */
+panel_status panel_thwaites(const panel_plan *plan, const void *ws, const double *gamma, const double *cl,
+                            double re, double *cd, double *ld, int32_t *sep, void *stream);
+
 /* Reverse-mode sensitivity of the forces outputs to every node (the shape
  * gradient of the Sec. 2 system, M(P) x = r(P, alpha)):
  *   dxy[2k + c] = sum over the airfoil's angles a of

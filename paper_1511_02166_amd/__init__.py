@@ -38,6 +38,7 @@ from ._binding import (  # noqa: F401
     panel_plan_set_wave_limit,
     panel_solve_noalloc,
     panel_status_str,
+    panel_thwaites,
     panel_workspace_init,
     panel_workspace_layout,
     panel_workspace_size,
@@ -50,5 +51,5 @@ __all__ = [
     "panel_plan_create", "panel_plan_destroy", "panel_plan_set_wave_limit", "panel_plan_set_tiling",
     "panel_plan_get_tiling", "panel_plan_set_formulation", "panel_workspace_size", "panel_workspace_init", "panel_workspace_layout",
     "panel_assemble", "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
-    "panel_naca4_vjp", "panel_math_eval", "panel_solve_noalloc", "PANEL_NOALLOC_MAX_BYTES", "panel_status_str", "panel_last_error", "load_library", "lib_path",
+    "panel_naca4_vjp", "panel_thwaites", "panel_math_eval", "panel_solve_noalloc", "PANEL_NOALLOC_MAX_BYTES", "panel_status_str", "panel_last_error", "load_library", "lib_path",
 ]

@@ -61,6 +61,7 @@ def load_library():
     L.panel_forces.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.panel_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.panel_naca4.argtypes = [i32, vp, i32, vp, vp, vp]
+    L.panel_thwaites.argtypes = [vp, vp, vp, vp, f64, vp, vp, vp, vp]
     L.panel_naca4_vjp.argtypes = [i32, vp, i32, vp, vp, vp, vp]
     L.panel_math_eval.argtypes = [i32, vp, vp, vp, vp, vp]
     L.panel_solve_noalloc.argtypes = [vp, vp, vp, vp, f64, f64, i32, vp, vp, vp, vp, vp, vp]
@@ -72,7 +73,7 @@ def load_library():
                  "panel_plan_set_formulation",
                  "panel_workspace_size", "panel_workspace_init",
                  "panel_workspace_layout", "panel_assemble",
-                 "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4",
+                 "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4", "panel_thwaites",
                  "panel_naca4_vjp", "panel_math_eval", "panel_solve_noalloc"):
         getattr(L, name).restype = C.c_int32
     _lib = L
@@ -236,6 +237,14 @@ def panel_forces(plan: Plan, ws, gamma, cp, cl, cl_p, stream=None):
     _check(load_library().panel_forces(plan.handle, _ptr(ws, torch.uint8, "ws"),
                                        _ptr(gamma, d, "gamma", True), _ptr(cp, d, "cp", True),
                                        _ptr(cl, d, "cl"), _ptr(cl_p, d, "cl_p", True), _stream(stream)))
+
+
+def panel_thwaites(plan: Plan, ws, gamma, cl, re, cd, ld, sep, stream=None):
+    import torch
+    d = torch.float64
+    _check(load_library().panel_thwaites(plan.handle, _ptr(ws, torch.uint8, "ws"), _ptr(gamma, d, "gamma"),
+                                         _ptr(cl, d, "cl"), float(re), _ptr(cd, d, "cd"), _ptr(ld, d, "ld"),
+                                         _ptr(sep, torch.int32, "sep"), _stream(stream)))
 
 
 def panel_adjoint(plan: Plan, ws, xy, dcl, dcp, dxy, info=None, stream=None):

@@ -389,6 +389,18 @@ panel_status panel_forces(const panel_plan *plan, const void *ws, double *gamma,
     return check_hip(e, "forces launch");
 }
 
+panel_status panel_thwaites(const panel_plan *plan, const void *ws, const double *gamma, const double *cl,
+                            double re, double *cd, double *ld, int32_t *sep, void *stream) {
+    if (!plan || !ws || !gamma || !cl || !cd || !ld || !sep) return fail(PANEL_EINVAL, "NULL argument");
+    if (!aligned8(gamma) || !aligned8(cl) || !aligned8(cd) || !aligned8(ld) || (reinterpret_cast<uintptr_t>(sep) & 3u))
+        return fail(PANEL_EINVAL, "arrays must be aligned (8 bytes; sep 4 bytes)");
+    if (!(std::isfinite(re) && re > 0.0)) return fail(PANEL_EINVAL, "re must be finite and > 0");
+    WsView v = ws_view(const_cast<void *>(ws), plan->layout);
+    hipError_t e = launch_thwaites(v, plan->B, plan->max_k, gamma, cl, re, cd, ld, sep,
+                                   static_cast<hipStream_t>(stream));
+    return check_hip(e, "viscous correction launch");
+}
+
 panel_status panel_adjoint(const panel_plan *plan, const void *ws, const double *xy,
                            const double *dcl, const double *dcp, double *dxy, int32_t *info,
                            void *stream) {

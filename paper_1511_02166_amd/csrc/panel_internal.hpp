@@ -113,6 +113,9 @@ hipError_t launch_refine_wave(const WsView &v, int32_t first, int32_t count, int
                               int32_t max_iter, hipStream_t stream);
 hipError_t launch_forces(const WsView &v, int32_t B, int32_t max_k, double *gamma, double *cp,
                          double *cl, double *cl_p, hipStream_t stream);
+// Viscous correction (viscous.hip): one wavefront per (airfoil, angle).
+hipError_t launch_thwaites(const WsView &v, int32_t B, int32_t max_k, const double *gamma, const double *cl,
+                           double re, double *cd, double *ld, int32_t *sep, hipStream_t stream);
 // Hess-Smith formulation (assemble_hs.hip): assembly + Kutta row, and forces.
 hipError_t launch_assemble_hs(const WsView &v, int32_t B, int32_t max_ld, int32_t mixed, const double *xy,
                               const double *alpha, const double *chord, double vinf, hipStream_t stream);

@@ -195,6 +195,16 @@ class PanelSolver:
         self.step(xy, alpha, chord, vinf, refine_tol, max_iter)
         return dict(gamma=self.gamma, cp=self.cp, cl=self.cl, cl_p=self.cl_p, info=self.info)
 
+    def viscous(self, re: float):
+        """Thwaites' laminar correction on the last forces' surface speeds:
+        dict(cd, ld, sep) (see panel_thwaites in include/panel.h)."""
+        p = self.plan
+        cd = torch.empty(p.n_alpha, dtype=torch.float64, device=self.device)
+        ld = torch.empty_like(cd)
+        sep = torch.empty(2 * p.n_alpha, dtype=torch.int32, device=self.device)
+        B.panel_thwaites(p, self.ws, self.gamma, self.cl, re, cd, ld, sep)
+        return dict(cd=cd, ld=ld, sep=sep)
+
     def adjoint(self, xy, dcl, dcp=None, out=None):
         """d/d(nodes) of sum(dcl * cl) + sum(dcp * cp) for the last step's
         factors (per-airfoil status in ``adj_info``)."""
