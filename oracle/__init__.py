@@ -117,6 +117,9 @@ def lib():
         L.oracle_hs_solve_batch.argtypes = [C.c_int, _ip, _dp, _ip, _dp, C.c_void_p, C.c_double,
                                             _dp, _dp, _dp, _dp, _ip, C.c_int]
         L.oracle_hs_solve_batch.restype = C.c_int
+        L.oracle_hs_force_gradient.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_double,
+                                                C.c_double, C.c_void_p, _dp]
+        L.oracle_hs_force_gradient.restype = C.c_int
         L.oracle_thwaites_surface.argtypes = [C.c_int, _dp, _dp, C.c_double, _dp, _dp]
         L.oracle_thwaites_surface.restype = C.c_int
         L.oracle_thwaites.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp, _dp, C.c_double, C.c_double,
@@ -310,7 +313,7 @@ def cl_gradient(xy, alpha, vinf=1.0, chord=1.0, with_alpha=False):
     return g.reshape(N + 1, 2)
 
 
-def force_gradient(xy, alpha, dcl=1.0, dcp=None, vinf=1.0, chord=1.0):
+def force_gradient(xy, alpha, dcl=1.0, dcp=None, vinf=1.0, chord=1.0, formulation="stream"):
     """d/dP of dcl * Cl + sum_i dcp[i] Cp_i for one angle: [N+1, 2]."""
     xy = _f64(xy).reshape(-1)
     N = xy.size // 2 - 1
@@ -320,8 +323,9 @@ def force_gradient(xy, alpha, dcl=1.0, dcp=None, vinf=1.0, chord=1.0):
         w = _f64(dcp).reshape(-1)
         if w.size != N:
             raise ValueError("dcp must hold one value per panel")
-    info = lib().oracle_force_gradient(N, xy, float(alpha), float(vinf), float(chord), float(dcl),
-                                       None if w is None else w.ctypes.data_as(C.c_void_p), g)
+    fn = {"stream": lib().oracle_force_gradient, "hess_smith": lib().oracle_hs_force_gradient}[formulation]
+    info = fn(N, xy, float(alpha), float(vinf), float(chord), float(dcl),
+              None if w is None else w.ctypes.data_as(C.c_void_p), g)
     if info != 0:
         raise RuntimeError(f"oracle gradient failed, info={info}")
     return g.reshape(N + 1, 2)

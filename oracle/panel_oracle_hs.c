@@ -219,3 +219,162 @@ int oracle_hs_solve_batch(int B, const int *node_off, const double *xy, const in
     free(sol_off);
     return used;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Gradient of the weighted forces of one angle in the Hess-Smith scheme,
+ *     F = dcl * Cl + sum_j dcp[j] * Cp_j,
+ * with respect to every node coordinate (grad[2k + c], k = 0..N): for each
+ * coordinate the whole complex-valued assembly is re-evaluated with that
+ * coordinate moved by i*h (complex step, Squire & Trapp 1998), giving dM,
+ * dR and the derivative of the tangential matrix and of the free-stream
+ * tangential speeds; then dx = M^{-1}(dR - dM x) with the real factors, and
+ * du = dMt x + Mt dx + d(V_inf . t), dF from u and the panel lengths.
+ * O(N^3) per coordinate: for small N only.                                 */
+#include <complex.h>
+
+#define HS_H 1e-30
+
+typedef double complex cplx;
+
+static cplx c_atan2(cplx y, cplx x)
+{
+    double yr = creal(y), xr = creal(x);
+    return atan2(yr, xr) + I * ((xr * cimag(y) - yr * cimag(x)) / (xr * xr + yr * yr));
+}
+
+static void c_frame(const cplx *z, int i, cplx *L, cplx *tx, cplx *ty)
+{
+    cplx hx = z[2 * i + 2] - z[2 * i], hy = z[2 * i + 3] - z[2 * i + 1];
+    *L = csqrt(hx * hx + hy * hy);
+    *tx = hx / *L;
+    *ty = hy / *L;
+}
+
+static void c_influence(const cplx *z, int i, cplx x, cplx y, int self, cplx *sx, cplx *sy, cplx *wx, cplx *wy)
+{
+    cplx L, tx, ty;
+    c_frame(z, i, &L, &tx, &ty);
+    cplx nx = ty, ny = -tx, lg, beta;
+    if (self) {
+        lg = 0.0;
+        beta = HS_PI;
+    } else {
+        cplx dx = x - z[2 * i], dy = y - z[2 * i + 1];
+        cplx xi = dx * tx + dy * ty, eta = dx * nx + dy * ny;
+        lg = 0.5 * (clog(xi * xi + eta * eta) - clog((xi - L) * (xi - L) + eta * eta));
+        beta = c_atan2(eta, xi - L) - c_atan2(eta, xi);
+    }
+    cplx us = lg / (2.0 * HS_PI), vs = beta / (2.0 * HS_PI);
+    *sx = us * tx + vs * nx;
+    *sy = us * ty + vs * ny;
+    *wx = vs * tx - us * nx;
+    *wy = vs * ty - us * ny;
+}
+
+/* complex system: M [(N+1)^2], R [N+1], Mt [N*(N+1)], tangential free-stream
+ * speeds ft [N] = V_inf . t_j, panel lengths Ls [N]                         */
+static void c_assemble(int N, const cplx *z, double alpha, double vinf, cplx *M, cplx *R, cplx *Mt, cplx *ft,
+                       cplx *Ls)
+{
+    const int n1 = N + 1;
+    const double ca = cos(alpha), sa = sin(alpha);
+    for (int j = 0; j < N; ++j) {
+        cplx Lj, tjx, tjy;
+        c_frame(z, j, &Lj, &tjx, &tjy);
+        Ls[j] = Lj;
+        cplx njx = tjy, njy = -tjx;
+        cplx mx = 0.5 * (z[2 * j] + z[2 * j + 2]), my = 0.5 * (z[2 * j + 1] + z[2 * j + 3]);
+        cplx vn = 0.0, vt = 0.0;
+        for (int i = 0; i < N; ++i) {
+            cplx sx, sy, wx, wy;
+            c_influence(z, i, mx, my, i == j, &sx, &sy, &wx, &wy);
+            M[j * n1 + i] = sx * njx + sy * njy;
+            Mt[j * n1 + i] = sx * tjx + sy * tjy;
+            vn += wx * njx + wy * njy;
+            vt += wx * tjx + wy * tjy;
+        }
+        M[j * n1 + N] = vn;
+        Mt[j * n1 + N] = vt;
+        R[j] = -vinf * (ca * tjy - sa * tjx);
+        ft[j] = vinf * (ca * tjx + sa * tjy);
+    }
+    for (int i = 0; i < n1; ++i)
+        M[N * n1 + i] = Mt[i] + Mt[(N - 1) * n1 + i];
+    cplx L0, t0x, t0y, Le, tex, tey;
+    c_frame(z, 0, &L0, &t0x, &t0y);
+    c_frame(z, N - 1, &Le, &tex, &tey);
+    R[N] = -vinf * (ca * (t0x + tex) + sa * (t0y + tey));
+}
+
+int oracle_hs_force_gradient(int N, const double *xy, double alpha, double vinf, double chord, double dcl,
+                             const double *dcp, double *grad)
+{
+    const int n1 = N + 1, nc = 2 * (N + 1);
+    cplx *z = malloc(sizeof(cplx) * (size_t)nc);
+    cplx *M = malloc(sizeof(cplx) * (size_t)n1 * n1);
+    cplx *Mt = malloc(sizeof(cplx) * (size_t)n1 * n1);
+    cplx *R = malloc(sizeof(cplx) * (size_t)n1);
+    cplx *ft = malloc(sizeof(cplx) * (size_t)N);
+    cplx *Ls = malloc(sizeof(cplx) * (size_t)N);
+    double *A = malloc(sizeof(double) * (size_t)n1 * n1);
+    double *x = malloc(sizeof(double) * (size_t)n1);
+    double *v = malloc(sizeof(double) * (size_t)n1);
+    double *Mtr = malloc(sizeof(double) * (size_t)n1 * n1);
+    double *u = malloc(sizeof(double) * (size_t)N);
+    int *piv = malloc(sizeof(int) * (size_t)n1);
+    for (int q = 0; q < nc; ++q)
+        z[q] = xy[q];
+    c_assemble(N, z, alpha, vinf, M, R, Mt, ft, Ls);
+    for (int q = 0; q < n1 * n1; ++q) {
+        A[q] = creal(M[q]);
+        Mtr[q] = creal(Mt[q]);
+    }
+    for (int j = 0; j < n1; ++j)
+        x[j] = creal(R[j]);
+    int info = oracle_lu(n1, A, piv);
+    if (info == 0) {
+        oracle_lu_solve(n1, A, piv, 1, x);
+        for (int j = 0; j < N; ++j) {
+            double s = creal(ft[j]);
+            for (int i = 0; i < n1; ++i)
+                s += Mtr[j * n1 + i] * x[i];
+            u[j] = s;
+        }
+        const double scale = -2.0 / (vinf * chord);
+        for (int q = 0; q < nc; ++q) {
+            z[q] = xy[q] + I * HS_H;
+            c_assemble(N, z, alpha, vinf, M, R, Mt, ft, Ls);
+            for (int j = 0; j < n1; ++j) {
+                double s = cimag(R[j]) / HS_H;
+                for (int i = 0; i < n1; ++i)
+                    s -= cimag(M[j * n1 + i]) / HS_H * x[i];
+                v[j] = s;
+            }
+            oracle_lu_solve(n1, A, piv, 1, v);   /* dx */
+            double dF = 0.0;
+            for (int j = 0; j < N; ++j) {
+                double du = cimag(ft[j]) / HS_H;
+                for (int i = 0; i < n1; ++i)
+                    du += cimag(Mt[j * n1 + i]) / HS_H * x[i] + Mtr[j * n1 + i] * v[i];
+                dF += dcl * scale * (du * creal(Ls[j]) + u[j] * cimag(Ls[j]) / HS_H);
+                if (dcp)
+                    dF += dcp[j] * (-2.0 * u[j] * du / (vinf * vinf));
+            }
+            grad[q] = dF;
+            z[q] = xy[q];
+        }
+    }
+    free(z);
+    free(M);
+    free(Mt);
+    free(R);
+    free(ft);
+    free(Ls);
+    free(A);
+    free(x);
+    free(v);
+    free(Mtr);
+    free(u);
+    free(piv);
+    return info;
+}

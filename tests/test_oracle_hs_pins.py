@@ -161,3 +161,46 @@ def test_hs_batch_packing_matches_single_calls():
         assert np.array_equal(r["gamma"][so:so + Ns[b] * Ks[b]], one["gamma"].reshape(-1))
         assert np.array_equal(r["cl"][aoff[b]:aoff[b + 1]], one["cl"])
         so += Ns[b] * Ks[b]
+
+
+def _hs_weighted(xy, a, dcl, dcp, vinf=1.0, chord=1.0):
+    r = oracle.solve_airfoil(xy, [a], vinf=vinf, chord=chord, formulation=HS)
+    return dcl * r["cl"][0] + float(np.dot(dcp, r["cp"][0]))
+
+
+def test_hs_gradient_vs_central_differences():
+    # d/dP of dcl Cl + sum dcp_j Cp_j (complex-step tangent-linear) against
+    # central differences of the Hess-Smith forward solve
+    N, a, h, vinf, chord = 20, 5 * DEG, 1e-6, 1.6, 0.8
+    xy = oracle.naca4(0.04, 0.35, 0.13, N)
+    dcp = np.random.default_rng(5).standard_normal(N)
+    g = oracle.force_gradient(xy, a, 0.7, dcp, vinf, chord, formulation=HS)
+    fd = np.zeros_like(xy)
+    for k in range(N + 1):
+        for c in range(2):
+            p, m = xy.copy(), xy.copy()
+            p[k, c] += h
+            m[k, c] -= h
+            fd[k, c] = (_hs_weighted(p, a, 0.7, dcp, vinf, chord) - _hs_weighted(m, a, 0.7, dcp, vinf, chord)) / (2 * h)
+    assert np.max(np.abs(g - fd)) < 1e-6 * np.max(np.abs(fd))
+
+
+def test_hs_gradient_invariants():
+    # translation: gradients sum to zero; scaling with the chord fixed:
+    # sum_k P_k . grad Cl = Cl and sum_k P_k . grad Cp_j = 0 (the surface speed
+    # is scale invariant); rotation: sum_k P_k^perp . grad F = -dF/dalpha
+    N, a = 40, 4 * DEG
+    xy = oracle.naca4(0.02, 0.45, 0.14, N)
+    dcp = np.random.default_rng(6).standard_normal(N)
+    gl = oracle.force_gradient(xy, a, 1.0, None, formulation=HS)
+    gp = oracle.force_gradient(xy, a, 0.0, dcp, formulation=HS)
+    cl = oracle.solve_airfoil(xy, [a], formulation=HS)["cl"][0]
+    for g in (gl, gp):
+        assert np.max(np.abs(g.sum(0))) < 1e-9 * np.max(np.abs(g))
+    assert abs((xy * gl).sum() - cl) < 1e-9
+    assert abs((xy * gp).sum()) < 1e-9 * np.max(np.abs(gp))
+    h = 1e-6
+    dfa = (_hs_weighted(xy, a + h, 0.3, dcp) - _hs_weighted(xy, a - h, 0.3, dcp)) / (2 * h)
+    g = 0.3 * gl + gp
+    perp = np.stack([-xy[:, 1], xy[:, 0]], 1)
+    assert abs((perp * g).sum() + dfa) < 1e-6 * max(1.0, abs(dfa))
