@@ -124,8 +124,8 @@ panel_status panel_plan_set_wave_limit(panel_plan *plan, int32_t max_n1);
  * matrix (one more system-sized section), so call this before
  * panel_workspace_size.  panel_forces reports, for both, the tangential
  * surface speed at the panel midpoints (the `gamma` output), Cp, Cl from the
- * circulation -2 sum_i u_i L_i / (vinf c) and Cl_p.  panel_adjoint supports
- * the stream-function formulation only (PANEL_EUNSUPPORTED otherwise).     */
+ * circulation -2 sum_i u_i L_i / (vinf c) and Cl_p; panel_adjoint
+ * differentiates either.                                                  */
 panel_status panel_plan_set_formulation(panel_plan *plan, int32_t formulation);
 
 /* How the factorisation maps a batch onto the GPU (Sec. 3: many independent
@@ -245,8 +245,10 @@ panel_status panel_thwaites(const panel_plan *plan, const void *ws, const double
  * (dCp_i/dgamma_i = -2 gamma_i / vinf^2).  Uses the factors left in the
  * workspace by panel_factor_solve (transposed solve; refined in FP64 for
  * PANEL_FP32_REFINE) and re-evaluates the assembly derivatives on the fly.
- * Without dcp one pass serves every angle; with dcp the work is one pass
- * per angle index.
+ * Stream function: without dcp one pass serves every angle; with dcp the
+ * work is one pass per angle index.  Hess-Smith (gamma is the surface speed
+ * u = T x + vinf e.t): one transposed solve per angle, lambda = M^-T T^T
+ * dF/du, with the tangential matrix kept by panel_assemble.
  *   xy     the node array passed to panel_assemble
  *   dcl    alpha_offsets[B] cotangents of cl
  *   dcp    cotangents of cp in panel_forces' layout, or NULL (all zero)

@@ -132,89 +132,16 @@ __device__ void solve_transposed(const T *LU, int ld, int n, const int *perm, V 
     __syncthreads();
 }
 
+// lambda = M^{-T} w for airfoil mt: w in tmp on entry, lambda in lam on exit
+// (tmp clobbered).  FP64 factors: one transposed solve.  FP32 factors:
+// lambda from U^T/L^T in FP32, then FP64 refinement of the transposed system
+// against the FP64 matrix kept in A64.  Returns false when the refinement ran
+// out of sweeps.
 template <typename T>
-__global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__restrict__ xy,
-                                                      const double *__restrict__ dcl,
-                                                      const double *__restrict__ dcp, int32_t ka,
-                                                      double *__restrict__ dxy, int32_t *__restrict__ info) {
-    const int b = v.order[blockIdx.x];
-    const AirfoilMeta mt = v.meta[b];
-    const int N = mt.N, n1 = mt.n1, K = mt.K, ld = mt.ld;
+__device__ bool solve_lambda(const WsView &v, const AirfoilMeta &mt, const int *perm, double *lam, double *tmp,
+                             T *sblk, double *part, double (*red)[TPB / 64]) {
+    const int n1 = mt.n1, ld = mt.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double *out = dxy + 2 * (size_t)mt.node_off;
-    if (ka >= K) return;   // per-angle pass past this airfoil's angles
-    if (v.flag[b] != 0) {
-        for (int k = tid; k < 2 * (N + 1); k += TPB) out[k] = __builtin_nan("");
-        if (info && tid == 0) info[b] = v.flag[b];
-        return;
-    }
-    __shared__ double sx[PANEL_NMAX + 1], sy[PANEL_NMAX + 1];
-    __shared__ double xbar[PANEL_NMAX + 1], lam[PANEL_NMAX + 1];
-    __shared__ double tmp[PANEL_NMAX + 1];
-    __shared__ double gmx[PANEL_NMAX], gmy[PANEL_NMAX];
-    __shared__ int perm[PANEL_NMAX + 1];
-    __shared__ T sblk[SB * SB];
-    __shared__ double part[(TPB / 64) * SB];
-    __shared__ double red[2][TPB / 64];
-
-    const double *P = xy + 2 * (size_t)mt.node_off;
-    for (int k = tid; k <= N; k += TPB) {
-        sx[k] = P[2 * k];
-        sy[k] = P[2 * k + 1];
-    }
-    const double vinf = v.hdr->vinf, chord = v.chord[b];
-    const double *X = v.x + mt.x_off;
-    // Cotangent seeds: all angles at once with cl cotangents only (ka < 0,
-    // one transposed solve; xbar = sum_k dcl_k x_k), or one angle with its
-    // cl and cp cotangents (ka >= 0; xbar = x_ka, the explicit length term
-    // scaled by dcl_ka).
-    double S = 0.0, Cc = 0.0, escale = 1.0;
-    if (ka < 0) {
-        for (int k = 0; k < K; ++k) {
-            const double a = v.alpha[mt.alpha_off + k], d = dcl[mt.alpha_off + k];
-            S += d * sin(a);
-            Cc += d * cos(a);
-        }
-    } else {
-        const double a = v.alpha[mt.alpha_off + ka];
-        S = sin(a);
-        Cc = cos(a);
-        escale = dcl[mt.alpha_off + ka];
-    }
-    const double *cpbar = (ka >= 0 && dcp) ? dcp + mt.s_off + (size_t)ka * N : nullptr;
-    const double cpf = -2.0 / (vinf * vinf);
-    for (int i = tid; i < n1; i += TPB) {
-        double s = 0.0;
-        if (ka < 0) {
-            for (int k = 0; k < K; ++k) s += dcl[mt.alpha_off + k] * X[(size_t)k * n1 + i];
-        } else {
-            s = X[(size_t)ka * n1 + i];
-        }
-        xbar[i] = s;
-    }
-    if (tid == 0) {
-        const int32_t *piv = v.piv + mt.piv_off;
-        for (int i = 0; i < n1; ++i) perm[i] = i;
-        for (int i = 0; i < n1; ++i) {
-            const int p = piv[i];
-            const int t0 = perm[i];
-            perm[i] = perm[p];
-            perm[p] = t0;
-        }
-    }
-    __syncthreads();
-    const double wscale = -2.0 / (vinf * chord);
-    for (int i = tid; i < n1; i += TPB) {
-        double w = 0.0;
-        if (i < N) {
-            const double hx = sx[i + 1] - sx[i], hy = sy[i + 1] - sy[i];
-            w = escale * wscale * sqrt(hx * hx + hy * hy);
-            if (cpbar) w += cpbar[i] * cpf * xbar[i];
-        }
-        tmp[i] = w;
-    }
-    __syncthreads();
-
     const T *LU = factors<T>(v, mt);
     bool conv = true;
     if constexpr (sizeof(T) == 8) {
@@ -297,6 +224,93 @@ __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__
             }
         }
     }
+    return conv;
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__restrict__ xy,
+                                                      const double *__restrict__ dcl,
+                                                      const double *__restrict__ dcp, int32_t ka,
+                                                      double *__restrict__ dxy, int32_t *__restrict__ info) {
+    const int b = v.order[blockIdx.x];
+    const AirfoilMeta mt = v.meta[b];
+    const int N = mt.N, n1 = mt.n1, K = mt.K;
+    const int tid = threadIdx.x;
+    double *out = dxy + 2 * (size_t)mt.node_off;
+    if (ka >= K) return;   // per-angle pass past this airfoil's angles
+    if (v.flag[b] != 0) {
+        for (int k = tid; k < 2 * (N + 1); k += TPB) out[k] = __builtin_nan("");
+        if (info && tid == 0) info[b] = v.flag[b];
+        return;
+    }
+    __shared__ double sx[PANEL_NMAX + 1], sy[PANEL_NMAX + 1];
+    __shared__ double xbar[PANEL_NMAX + 1], lam[PANEL_NMAX + 1];
+    __shared__ double tmp[PANEL_NMAX + 1];
+    __shared__ double gmx[PANEL_NMAX], gmy[PANEL_NMAX];
+    __shared__ int perm[PANEL_NMAX + 1];
+    __shared__ T sblk[SB * SB];
+    __shared__ double part[(TPB / 64) * SB];
+    __shared__ double red[2][TPB / 64];
+
+    const double *P = xy + 2 * (size_t)mt.node_off;
+    for (int k = tid; k <= N; k += TPB) {
+        sx[k] = P[2 * k];
+        sy[k] = P[2 * k + 1];
+    }
+    const double vinf = v.hdr->vinf, chord = v.chord[b];
+    const double *X = v.x + mt.x_off;
+    // Cotangent seeds: all angles at once with cl cotangents only (ka < 0,
+    // one transposed solve; xbar = sum_k dcl_k x_k), or one angle with its
+    // cl and cp cotangents (ka >= 0; xbar = x_ka, the explicit length term
+    // scaled by dcl_ka).
+    double S = 0.0, Cc = 0.0, escale = 1.0;
+    if (ka < 0) {
+        for (int k = 0; k < K; ++k) {
+            const double a = v.alpha[mt.alpha_off + k], d = dcl[mt.alpha_off + k];
+            S += d * sin(a);
+            Cc += d * cos(a);
+        }
+    } else {
+        const double a = v.alpha[mt.alpha_off + ka];
+        S = sin(a);
+        Cc = cos(a);
+        escale = dcl[mt.alpha_off + ka];
+    }
+    const double *cpbar = (ka >= 0 && dcp) ? dcp + mt.s_off + (size_t)ka * N : nullptr;
+    const double cpf = -2.0 / (vinf * vinf);
+    for (int i = tid; i < n1; i += TPB) {
+        double s = 0.0;
+        if (ka < 0) {
+            for (int k = 0; k < K; ++k) s += dcl[mt.alpha_off + k] * X[(size_t)k * n1 + i];
+        } else {
+            s = X[(size_t)ka * n1 + i];
+        }
+        xbar[i] = s;
+    }
+    if (tid == 0) {
+        const int32_t *piv = v.piv + mt.piv_off;
+        for (int i = 0; i < n1; ++i) perm[i] = i;
+        for (int i = 0; i < n1; ++i) {
+            const int p = piv[i];
+            const int t0 = perm[i];
+            perm[i] = perm[p];
+            perm[p] = t0;
+        }
+    }
+    __syncthreads();
+    const double wscale = -2.0 / (vinf * chord);
+    for (int i = tid; i < n1; i += TPB) {
+        double w = 0.0;
+        if (i < N) {
+            const double hx = sx[i + 1] - sx[i], hy = sy[i + 1] - sy[i];
+            w = escale * wscale * sqrt(hx * hx + hy * hy);
+            if (cpbar) w += cpbar[i] * cpf * xbar[i];
+        }
+        tmp[i] = w;
+    }
+    __syncthreads();
+
+    const bool conv = solve_lambda<T>(v, mt, perm, lam, tmp, sblk, part, red);
     // info: 0, or -2 when the FP64 refinement of lambda ran out of sweeps
     // (a later per-angle pass never clears an earlier failure)
     if (info && tid == 0) {
@@ -416,7 +430,239 @@ __global__ __launch_bounds__(TPB) void adjoint_kernel(WsView v, const double *__
     }
 }
 
+// ---- Hess-Smith formulation ------------------------------------------------
+// Unknowns x = (q_0..q_{N-1}, g): source densities and the shared vortex
+// density; surface speed u = T x + V_inf e.t (T: the tangential matrix kept
+// by the assembly), Cl = -2 sum_j u_j L_j / (V_inf c), Cp_j = 1 - u_j^2/V_inf^2.
+// For each angle, with g_j = dF/du_j, w = T^T g and lambda = M^{-T} w, the
+// source-block entries A_ji (normal) and T_ji (tangential), i != j, carry the
+// weights
+//   W_A(j,i) = g_j x_N - lambda_j x_i - k_j lambda_N x_N
+//   W_T(j,i) = g_j x_i + lambda_j x_N - k_j lambda_N x_i
+// (k_j = 1 on the two trailing-edge rows that form the Kutta row; the
+// vortex columns are row sums of the source blocks, so their derivatives
+// fold into these weights).  A and T depend on d1 = m_j - P_i, d2 = m_j -
+// P_{i+1} through lg = log(|d1|/|d2|) and the subtended angle beta, and on
+// the panel angles through c = t_i.t_j = cos(phi_j - phi_i), s = t_i x t_j:
+//   d/dd1 (W_A A + W_T T) = (a d1 + b perp(d1)) / (2 pi |d1|^2)
+//   d/dd2 (W_A A + W_T T) = -(a d2 + b perp(d2)) / (2 pi |d2|^2)
+//   d/dphi_j = -d/dphi_i  = (lg b - beta a) / 2pi
+// with a = W_A s + W_T c, b = W_A c - W_T s, perp(v) = (-v_y, v_x).  The
+// right-hand sides (-V_inf e.n_j, and -V_inf e.(t_0 + t_{N-1}) on the Kutta
+// row), the free-stream part of u and the panel lengths in Cl add explicit
+// terms.  Self entries (A_jj = 1/2, T_jj = 0) are constants.
+// One workgroup per airfoil loops over its angles.  Pass 1 (a thread per
+// row j, walking the panels) sums the control-point and row-angle terms;
+// pass 2 (a thread per node k, walking the rows) sums the endpoint terms of
+// the panels starting and ending at node k and the column-angle term of
+// panel k.  All sums have a single owner thread; gradients w.r.t. the
+// midpoints (gm) and the panel vectors (gh = dF/dphi perp(t)/L + length
+// terms) reach the nodes at the end.
+template <typename T>
+__global__ __launch_bounds__(TPB) void adjoint_hs_kernel(WsView v, const double *__restrict__ xy,
+                                                         const double *__restrict__ dcl,
+                                                         const double *__restrict__ dcp,
+                                                         double *__restrict__ dxy, int32_t *__restrict__ info) {
+    const int b = v.order[blockIdx.x];
+    const AirfoilMeta mt = v.meta[b];
+    const int N = mt.N, n1 = mt.n1, K = mt.K, ld = mt.ld;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *out = dxy + 2 * (size_t)mt.node_off;
+    if (v.flag[b] != 0) {
+        for (int k = tid; k < 2 * (N + 1); k += TPB) out[k] = __builtin_nan("");
+        if (info && tid == 0) info[b] = v.flag[b];
+        return;
+    }
+    __shared__ double sx[PANEL_NMAX + 1], sy[PANEL_NMAX + 1];
+    __shared__ double xk[PANEL_NMAX + 1], lam[PANEL_NMAX + 1], gu[PANEL_NMAX + 1];
+    __shared__ double tmp[PANEL_NMAX + 1];
+    __shared__ double gmx[PANEL_NMAX], gmy[PANEL_NMAX], ghx[PANEL_NMAX], ghy[PANEL_NMAX];
+    __shared__ double gnx[PANEL_NMAX + 1], gny[PANEL_NMAX + 1];
+    __shared__ int perm[PANEL_NMAX + 1];
+    __shared__ T sblk[SB * SB];
+    __shared__ double part[(TPB / 64) * SB];
+    __shared__ double red[2][TPB / 64];
+
+    const double *P = xy + 2 * (size_t)mt.node_off;
+    for (int k = tid; k <= N; k += TPB) {
+        sx[k] = P[2 * k];
+        sy[k] = P[2 * k + 1];
+        gnx[k] = gny[k] = 0.0;
+    }
+    for (int j = tid; j < N; j += TPB) gmx[j] = gmy[j] = ghx[j] = ghy[j] = 0.0;
+    if (tid == 0) {
+        const int32_t *piv = v.piv + mt.piv_off;
+        for (int i = 0; i < n1; ++i) perm[i] = i;
+        for (int i = 0; i < n1; ++i) {
+            const int p = piv[i];
+            const int t0 = perm[i];
+            perm[i] = perm[p];
+            perm[p] = t0;
+        }
+    }
+    const double vinf = v.hdr->vinf, chord = v.chord[b];
+    const double lscale = -2.0 / (vinf * chord), cpf = -2.0 / (vinf * vinf);
+    const PanelGeom *geo = v.geom + mt.panel_off;
+    const double *Tg = v.tg + mt.a_off;
+    bool conv = true;
+    __syncthreads();
+
+    for (int k = 0; k < K; ++k) {
+        const double a = v.alpha[mt.alpha_off + k], ex = cos(a), ey = sin(a);
+        const double dk = dcl[mt.alpha_off + k];
+        const double *cpbar = dcp ? dcp + mt.s_off + (size_t)k * N : nullptr;
+        for (int i = tid; i < n1; i += TPB) xk[i] = v.x[mt.x_off + (size_t)k * n1 + i];
+        __syncthreads();
+        // u_j = (T x)_j + V_inf e.t_j; g_j = dF/du_j; explicit length term
+        for (int j = tid; j < N; j += TPB) {
+            const PanelGeom g = geo[j];
+            double u = vinf * (ex * g.tx + ey * g.ty);
+            for (int i = 0; i < n1; ++i) u += Tg[(size_t)i * ld + j] * xk[i];
+            double gj = dk * lscale * g.L;
+            if (cpbar) gj += cpbar[j] * cpf * u;
+            gu[j] = gj;
+            const double el = dk * lscale * u;
+            ghx[j] += el * g.tx;
+            ghy[j] += el * g.ty;
+        }
+        __syncthreads();
+        // w = T^T g: a wavefront per column, lanes along the rows
+        for (int i = wave; i < n1; i += TPB / 64) {
+            const double *col = Tg + (size_t)i * ld;
+            double s = 0.0;
+            for (int j = lane; j < N; j += 64) s += col[j] * gu[j];
+            s = wave_sum(s);
+            if (lane == 0) tmp[i] = s;
+        }
+        __syncthreads();
+        conv = solve_lambda<T>(v, mt, perm, lam, tmp, sblk, part, red) && conv;
+        __syncthreads();
+        const double xN = xk[N], lN = lam[N];
+
+        // ---- pass 1: a thread per row j -----------------------------------
+        for (int j = tid; j < N; j += TPB) {
+            const PanelGeom gj = geo[j];
+            const double mx = 0.5 * (sx[j] + sx[j + 1]), my = 0.5 * (sy[j] + sy[j + 1]);
+            const double g = gu[j], lj = lam[j], kl = (j == 0 || j == N - 1) ? lN : 0.0;
+            const double wa0 = g * xN - kl * xN, wt0 = lj * xN;   // the parts of W_A, W_T free of x_i
+            const double wa1 = -lj, wt1 = g - kl;                  // ... and the factors of x_i
+            double d1x = mx - sx[0], d1y = my - sy[0];
+            double q1 = d1x * d1x + d1y * d1y, l1 = plog(q1);
+            double ax = 0.0, ay = 0.0, phi = 0.0;
+            for (int i = 0; i < N; ++i) {
+                const double d2x = mx - sx[i + 1], d2y = my - sy[i + 1];
+                const double q2 = d2x * d2x + d2y * d2y, l2 = plog(q2);
+                if (i != j) {
+                    const PanelGeom gi = geo[i];
+                    const double c = gi.tx * gj.tx + gi.ty * gj.ty, s = gi.tx * gj.ty - gi.ty * gj.tx;
+                    const double xi = xk[i];
+                    const double WA = wa0 + wa1 * xi, WT = wt0 + wt1 * xi;
+                    const double aa = WA * s + WT * c, bb = WA * c - WT * s;
+                    const double r1 = 1.0 / q1, r2 = 1.0 / q2;
+                    // (a d + b perp(d)) / |d|^2 at d1, minus the same at d2
+                    ax += (aa * d1x - bb * d1y) * r1 - (aa * d2x - bb * d2y) * r2;
+                    ay += (aa * d1y + bb * d1x) * r1 - (aa * d2y + bb * d2x) * r2;
+                    const double cr = d1x * d2y - d1y * d2x, dd = d1x * d2x + d1y * d2y;
+                    const double beta = patan2(-cr, dd), lg = 0.5 * (l1 - l2);
+                    phi += lg * bb - beta * aa;
+                }
+                d1x = d2x;
+                d1y = d2y;
+                q1 = q2;
+                l1 = l2;
+            }
+            gmx[j] += kInv2Pi * ax;
+            gmy[j] += kInv2Pi * ay;
+            // dF/dphi_j: matrix rows, right-hand side, free stream in u
+            const double et = ex * gj.tx + ey * gj.ty, ep = -ex * gj.ty + ey * gj.tx;   // e.t, e.perp(t)
+            const double dphi = kInv2Pi * phi - lj * vinf * et + g * vinf * ep - kl * vinf * ep;
+            const double f = dphi / gj.L;
+            ghx[j] += -f * gj.ty;
+            ghy[j] += f * gj.tx;
+        }
+
+        // ---- pass 2: a thread per node k ----------------------------------
+        for (int kn = tid; kn <= N; kn += TPB) {
+            const double px = sx[kn], py = sy[kn];
+            const bool has_s = kn < N, has_e = kn >= 1;   // panel kn starts / panel kn-1 ends here
+            PanelGeom gs{}, ge{};
+            double qx = 0.0, qy = 0.0, xs = 0.0, xe = 0.0;
+            if (has_s) {
+                gs = geo[kn];
+                qx = sx[kn + 1];
+                qy = sy[kn + 1];
+                xs = xk[kn];
+            }
+            if (has_e) {
+                ge = geo[kn - 1];
+                xe = xk[kn - 1];
+            }
+            double ex1 = 0.0, ey1 = 0.0, cphi = 0.0;
+            for (int j = 0; j < N; ++j) {
+                const PanelGeom gj = geo[j];
+                const double mx = 0.5 * (sx[j] + sx[j + 1]), my = 0.5 * (sy[j] + sy[j + 1]);
+                const double g = gu[j], lj = lam[j], kl = (j == 0 || j == N - 1) ? lN : 0.0;
+                const double wa0 = g * xN - kl * xN, wt0 = lj * xN, wa1 = -lj, wt1 = g - kl;
+                const double dx = mx - px, dy = my - py;
+                const double q = dx * dx + dy * dy, rq = 1.0 / q;
+                if (has_s && j != kn) {   // node kn is P_i of panel i = kn: -d/dd1
+                    const double c = gs.tx * gj.tx + gs.ty * gj.ty, s = gs.tx * gj.ty - gs.ty * gj.tx;
+                    const double WA = wa0 + wa1 * xs, WT = wt0 + wt1 * xs;
+                    const double aa = WA * s + WT * c, bb = WA * c - WT * s;
+                    ex1 -= (aa * dx - bb * dy) * rq;
+                    ey1 -= (aa * dy + bb * dx) * rq;
+                    const double d2x = mx - qx, d2y = my - qy;
+                    const double q2 = d2x * d2x + d2y * d2y;
+                    const double cr = dx * d2y - dy * d2x, dd = dx * d2x + dy * d2y;
+                    const double beta = patan2(-cr, dd), lg = 0.5 * (plog(q) - plog(q2));
+                    cphi += lg * bb - beta * aa;
+                }
+                if (has_e && j != kn - 1) {   // node kn is P_{i+1} of panel i = kn-1: -d/dd2
+                    const double c = ge.tx * gj.tx + ge.ty * gj.ty, s = ge.tx * gj.ty - ge.ty * gj.tx;
+                    const double WA = wa0 + wa1 * xe, WT = wt0 + wt1 * xe;
+                    const double aa = WA * s + WT * c, bb = WA * c - WT * s;
+                    ex1 += (aa * dx - bb * dy) * rq;
+                    ey1 += (aa * dy + bb * dx) * rq;
+                }
+            }
+            gnx[kn] += kInv2Pi * ex1;
+            gny[kn] += kInv2Pi * ey1;
+            if (has_s) {   // dF/dphi_kn from the column of panel kn
+                const double f = -kInv2Pi * cphi / gs.L;
+                ghx[kn] += -f * gs.ty;
+                ghy[kn] += f * gs.tx;
+            }
+        }
+        __syncthreads();
+    }
+    if (info && tid == 0) info[b] = conv ? 0 : -2;
+
+    // ---- node gradients: midpoints split evenly, panel vectors P_{i+1} - P_i
+    for (int kn = tid; kn <= N; kn += TPB) {
+        double gx = gnx[kn], gy = gny[kn];
+        if (kn >= 1) {
+            gx += 0.5 * gmx[kn - 1] + ghx[kn - 1];
+            gy += 0.5 * gmy[kn - 1] + ghy[kn - 1];
+        }
+        if (kn < N) {
+            gx += 0.5 * gmx[kn] - ghx[kn];
+            gy += 0.5 * gmy[kn] - ghy[kn];
+        }
+        out[2 * kn] = gx;
+        out[2 * kn + 1] = gy;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_adjoint_hs(const WsView &v, int32_t B, int32_t mixed, const double *xy, const double *dcl,
+                             const double *dcp, double *dxy, int32_t *info, hipStream_t stream) {
+    if (mixed)
+        adjoint_hs_kernel<float><<<B, TPB, 0, stream>>>(v, xy, dcl, dcp, dxy, info);
+    else
+        adjoint_hs_kernel<double><<<B, TPB, 0, stream>>>(v, xy, dcl, dcp, dxy, info);
+    return hipGetLastError();
+}
 
 hipError_t launch_adjoint(const WsView &v, int32_t B, int32_t n_block, int32_t max_k, int32_t mixed,
                           const double *xy, const double *dcl, const double *dcp, double *dxy, int32_t *info,

@@ -411,11 +411,12 @@ panel_status panel_adjoint(const panel_plan *plan, const void *ws, const double 
     if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(PANEL_EINVAL, "workspace must be 256-byte aligned");
     if (plan->order_stale)
         return fail(PANEL_EINVAL, "wave limit changed: call panel_workspace_init (and refactor) first");
-    if (plan->formulation != PANEL_STREAM_FUNCTION)
-        return fail(PANEL_EUNSUPPORTED, "the adjoint covers the stream-function formulation only");
     WsView v = ws_view(const_cast<void *>(ws), plan->layout);
-    hipError_t e = launch_adjoint(v, plan->B, plan->n_block, plan->max_k, plan->precision == PANEL_FP32_REFINE,
-                                  xy, dcl, dcp, dxy, info, static_cast<hipStream_t>(stream));
+    const int32_t mixed = plan->precision == PANEL_FP32_REFINE;
+    hipError_t e = plan->formulation == PANEL_HESS_SMITH
+                       ? launch_adjoint_hs(v, plan->B, mixed, xy, dcl, dcp, dxy, info, static_cast<hipStream_t>(stream))
+                       : launch_adjoint(v, plan->B, plan->n_block, plan->max_k, mixed, xy, dcl, dcp, dxy, info,
+                                        static_cast<hipStream_t>(stream));
     return check_hip(e, "adjoint launch");
 }
 

@@ -131,5 +131,9 @@ hipError_t launch_adjoint(const WsView &v, int32_t B, int32_t n_block, int32_t m
 hipError_t launch_adjoint_wave(const WsView &v, int32_t first, int32_t count, int32_t mixed, const double *xy,
                                const double *dcl, const double *dcp, int32_t ka, double *dxy, int32_t *info,
                                hipStream_t stream);
+// Hess-Smith formulation: one workgroup per airfoil, all angles, cl and (dcp
+// non-NULL) cp cotangents.
+hipError_t launch_adjoint_hs(const WsView &v, int32_t B, int32_t mixed, const double *xy, const double *dcl,
+                             const double *dcp, double *dxy, int32_t *info, hipStream_t stream);
 
 }  // namespace panel

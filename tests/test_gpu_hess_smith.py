@@ -175,10 +175,10 @@ def test_hs_closed_forms_on_the_gpu():
     assert errs[2] < 2e-4 and errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
 
 
-def test_hs_graph_replay_noalloc_and_adjoint_refusal():
+def test_hs_graph_replay_and_noalloc():
     import torch
     import paper_1511_02166_amd as P
-    _say("Hess-Smith: graph replay, no-alloc entry point, adjoint refusal")
+    _say("Hess-Smith: graph replay, no-alloc entry point")
     w = synth.workload("ga2048", B=64)
     s, xy, got = _solve(w, 0)
     alpha = torch.as_tensor(w.alpha_flat(), device="cuda")
@@ -202,5 +202,159 @@ def test_hs_graph_replay_noalloc_and_adjoint_refusal():
     P.panel_solve_noalloc(plan, xy, alpha, None, 1.0, 1e-10, 10, info, None, None, cl, None)
     torch.cuda.synchronize()
     assert torch.equal(cl, eager) and int(info.abs().max()) == 0
-    with pytest.raises(P.PanelError, match="stream-function"):
-        s.adjoint(xy, torch.ones(w.B, dtype=torch.float64, device="cuda"))
+
+
+# ---- shape gradient (panel_adjoint) in the Hess-Smith formulation ---------------
+
+
+def _hs_oracle_grad(xy_flat, noff, alphas, dcl, dcp_flat, vinf=1.0, chords=None):
+    out = np.zeros_like(xy_flat)
+    so = 0
+    for b in range(len(noff) - 1):
+        xyb = xy_flat[2 * noff[b]:2 * noff[b + 1]].reshape(-1, 2)
+        N = xyb.shape[0] - 1
+        c = 1.0 if chords is None else chords[b]
+        g = 0.0
+        for k in range(len(alphas[b])):
+            w = None if dcp_flat is None else dcp_flat[so + k * N:so + (k + 1) * N]
+            g = g + oracle.force_gradient(xyb, alphas[b][k], dcl[b][k], w, vinf, c, formulation=HS)
+        so += N * len(alphas[b])
+        out[2 * noff[b]:2 * noff[b + 1]] = g.reshape(-1)
+    return out
+
+
+def _hs_adjoint(xy_flat, noff, alphas, dcl, dcp=None, prec=0, vinf=1.0, chords=None):
+    import torch
+    import paper_1511_02166_amd as P
+    aoff = np.concatenate([[0], np.cumsum([len(a) for a in alphas])]).astype(np.int32)
+    s = P.PanelSolver(noff, aoff, prec, formulation=P.PANEL_HESS_SMITH)
+    xy = torch.as_tensor(xy_flat, device="cuda")
+    ch = None if chords is None else torch.as_tensor(np.asarray(chords, dtype=np.float64), device="cuda")
+    s.step(xy, torch.as_tensor(np.concatenate(alphas), device="cuda"), chord=ch, vinf=vinf)
+    g = s.adjoint(xy, torch.as_tensor(np.concatenate(dcl), device="cuda"),
+                  None if dcp is None else torch.as_tensor(dcp, device="cuda"))
+    torch.cuda.synchronize()
+    return g.cpu().numpy(), s
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-8)])
+@pytest.mark.parametrize("with_cp", [False, True], ids=["cl", "cl+cp"])
+def test_hs_adjoint_matches_oracle(precision, tol, with_cp):
+    # dxy of sum dcl Cl (+ sum dcp Cp) against the oracle's tangent-linear
+    # gradient (complex-step entry derivatives) on the same nodes: uneven N
+    # and K, chords and vinf != 1
+    _say(f"Hess-Smith adjoint, precision={precision}, cp cotangents={with_cp}")
+    ns = [24, 40, 64, 96, 130]
+    xy_flat, noff = synth.pack_nodes([oracle.naca4(0.01 * q, 0.3 + 0.05 * q, 0.1 + 0.015 * q, n)
+                                      for q, n in enumerate(ns)])
+    rng = np.random.default_rng(91)
+    Ks = [1, 3, 2, 1, 2]
+    alphas = [rng.uniform(-4, 10, k) * DEG for k in Ks]
+    dcl = [rng.standard_normal(k) for k in Ks]
+    dcp = rng.standard_normal(int(np.dot(ns, Ks))) if with_cp else None
+    chords = rng.uniform(0.5, 1.5, len(ns))
+    g, s = _hs_adjoint(xy_flat, noff, alphas, dcl, dcp, precision, vinf=1.4, chords=chords)
+    ref = _hs_oracle_grad(xy_flat, noff, alphas, dcl, dcp, 1.4, chords)
+    info = s.adj_info.cpu().numpy()
+    e = _rel(g, ref)
+    _say(f"  rel err {e:.3e}, info {list(info)}")
+    assert np.all(info == 0)
+    assert e < tol
+
+
+def test_hs_adjoint_invariants_and_central_differences():
+    # translation: the node gradients sum to zero; uniform scaling (chord
+    # held fixed) scales Cl linearly and leaves Cp unchanged, so
+    # sum_k P_k . dCl/dP_k = Cl and sum_k P_k . dCp_i/dP_k = 0; a random
+    # direction against central differences of the GPU's own forward
+    import torch
+    _say("Hess-Smith adjoint invariants")
+    nodes = [oracle.naca4(0.04, 0.4, 0.12, 128), synth.joukowski_nodes(200, 0.25, complex(-0.05, 0.03))]
+    xy_flat, noff = synth.pack_nodes(nodes)
+    alphas = [np.array([4 * DEG]), np.array([-2 * DEG, 6 * DEG])]
+    g, s = _hs_adjoint(xy_flat, noff, alphas, [np.ones(1), np.ones(2)])
+    cl = s.cl.cpu().numpy()
+    for b, ks in ((0, [0]), (1, [1, 2])):
+        gb = g[2 * noff[b]:2 * noff[b + 1]].reshape(-1, 2)
+        pb = xy_flat[2 * noff[b]:2 * noff[b + 1]].reshape(-1, 2)
+        assert np.max(np.abs(gb.sum(0))) < 1e-10 * np.max(np.abs(gb))
+        assert abs((gb * pb).sum() - cl[ks].sum()) < 1e-10 * max(1.0, abs(cl[ks].sum()))
+    # Cp cotangents only: scale invariance
+    S = int(s.gamma.numel())
+    dcp = np.random.default_rng(4).standard_normal(S)
+    gp, _ = _hs_adjoint(xy_flat, noff, alphas, [np.zeros(1), np.zeros(2)], dcp)
+    for b in range(2):
+        gb = gp[2 * noff[b]:2 * noff[b + 1]].reshape(-1, 2)
+        pb = xy_flat[2 * noff[b]:2 * noff[b + 1]].reshape(-1, 2)
+        assert abs((gb * pb).sum()) < 1e-10 * np.abs(gb * pb).sum()
+    # central differences of the GPU's own forward along a smooth direction
+    # on the NACA section (the cusped Joukowski edge has panels short enough
+    # that any usable step is far from the linear range), Richardson-
+    # extrapolated: O(h^4) truncation
+    d = np.zeros(xy_flat.size)
+    d[:2 * noff[1]] = np.convolve(np.random.default_rng(5).standard_normal(2 * noff[1]), np.ones(9) / 9, "same")
+    al = torch.as_tensor(np.concatenate(alphas), device="cuda")
+
+    def F(x):
+        s.step(torch.as_tensor(x, device="cuda"), al)
+        torch.cuda.synchronize()
+        return float(s.cl.sum())
+
+    def cd(h):
+        return (F(xy_flat + h * d) - F(xy_flat - h * d)) / (2 * h)
+    h = 1e-5
+    fd = (4 * cd(h / 2) - cd(h)) / 3
+    _say(f"  directional derivative {float(g @ d):.10f}, central differences {fd:.10f}")
+    assert abs(g @ d - fd) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_hs_autograd_cl_cp():
+    # panel_cl_cp's backward through the Hess-Smith adjoint
+    import torch
+    import paper_1511_02166_amd as P
+    _say("Hess-Smith autograd (cl, cp)")
+    xy_flat, noff = synth.pack_nodes([oracle.naca4(0.04, 0.4, 0.12, 48), oracle.naca4(0.01, 0.3, 0.15, 80)])
+    aoff = np.array([0, 1, 3], dtype=np.int32)
+    al_np = np.array([2.0, 5.0, -1.0]) * DEG
+    s = P.PanelSolver(noff, aoff, 0, formulation=P.PANEL_HESS_SMITH)
+    al = torch.as_tensor(al_np, device="cuda")
+    xy = torch.as_tensor(xy_flat, device="cuda").requires_grad_(True)
+    cl, cp = P.panel_cl_cp(xy, al, s)
+    rng = np.random.default_rng(12)
+    wcl = rng.standard_normal(3)
+    wcp = rng.standard_normal(cp.numel())
+    loss = (cl * torch.as_tensor(wcl, device="cuda")).sum() + (cp * torch.as_tensor(wcp, device="cuda")).sum()
+    loss.backward()
+    ref = _hs_oracle_grad(xy_flat, noff, [al_np[:1], al_np[1:]], [wcl[:1], wcl[1:]], wcp)
+    e = _rel(xy.grad.cpu().numpy(), ref)
+    _say(f"  rel err {e:.3e}")
+    assert e < 1e-9
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_hs_adjoint_ga_batch_2048(precision):
+    # the GA-population batch: every airfoil's translation invariant, two
+    # sampled airfoils against the oracle
+    import torch
+    import paper_1511_02166_amd as P
+    _say(f"Hess-Smith adjoint, 2048 x N=256, precision={precision}")
+    w = synth.workload("ga2048")
+    s, xy, got = _solve(w, precision)
+    dcl = np.random.default_rng(8).standard_normal(w.B)
+    g = s.adjoint(xy, torch.as_tensor(dcl, device="cuda")).cpu().numpy()
+    assert np.all(s.adj_info.cpu().numpy() == 0)
+    G = g.reshape(w.B, 257, 2)
+    tr = np.max(np.abs(G.sum(1))) / np.max(np.abs(G))
+    _say(f"  translation residual {tr:.1e}")
+    assert tr < 1e-10
+    xh = xy.cpu().numpy().reshape(w.B, 257, 2)
+    al = w.alpha_flat()
+    for b in (0, 1337):
+        ref = oracle.force_gradient(xh[b], al[b], dcl[b], formulation=HS)
+        e = _rel(G[b], ref)
+        _say(f"  airfoil {b}: rel err {e:.3e}")
+        assert e < (1e-9 if precision == 0 else 1e-8)
