@@ -30,6 +30,16 @@ Parity status per function (see the pins under ``tests/``):
                         (stagnation flow exact, power-law edge flows at second
                         order, the circular cylinder's closed-form drag and
                         separation angle, symmetry, Reynolds scaling)
+  oracle_bspline_*      B-spline contour of the genome (panel_oracle_ga.c):
+                        pinned (SciPy's BSpline, a different algorithm; the
+                        polyline at degree 1; linear precision at the
+                        Greville abscissae; endpoint interpolation, mirror
+                        symmetry)
+  oracle_ga_*           genetic-algorithm operators (panel_oracle_ga.c):
+                        pinned (tournament rank frequencies p(1-p)^r, the
+                        special cases k = 1 and p = 1 by brute force,
+                        crossover conservation, mutation bounds and rate,
+                        convergence on a quadratic fitness)
 """
 from __future__ import annotations
 
@@ -41,7 +51,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = [os.path.join(_HERE, "panel_oracle.c"), os.path.join(_HERE, "panel_oracle_grad.c"),
-        os.path.join(_HERE, "panel_oracle_hs.c"), os.path.join(_HERE, "panel_oracle_bl.c")]
+        os.path.join(_HERE, "panel_oracle_hs.c"), os.path.join(_HERE, "panel_oracle_bl.c"),
+        os.path.join(_HERE, "panel_oracle_ga.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -125,6 +136,19 @@ def lib():
         L.oracle_thwaites.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp, _dp, C.c_double, C.c_double,
                                       C.c_double, _dp, _dp, _ip]
         L.oracle_thwaites.restype = None
+        L.oracle_bspline_point.argtypes = [C.c_int, C.c_int, _dp, C.c_double, _dp]
+        L.oracle_bspline_point.restype = None
+        L.oracle_bspline_param.argtypes = [C.c_int, C.c_int]
+        L.oracle_bspline_param.restype = C.c_double
+        L.oracle_bspline_nodes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _ip, _dp, _dp]
+        L.oracle_bspline_nodes.restype = None
+        L.oracle_ga_init.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
+        L.oracle_ga_init.restype = None
+        L.oracle_ga_fitness.argtypes = [C.c_int, _ip, _dp, _ip, _dp]
+        L.oracle_ga_fitness.restype = None
+        L.oracle_ga_step.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, _dp, _dp,
+                                     _dp, _dp, _dp, _dp, _ip]
+        L.oracle_ga_step.restype = None
         _lib = L
     return _lib
 
@@ -343,3 +367,66 @@ def workload_nodes(w):
     parts = [naca4(w.m[b], w.p[b], w.t[b], int(w.n_panels[b]), w.closed_te) for b in range(w.B)]
     xy = np.concatenate([q.reshape(-1) for q in parts])
     return xy, w.node_offsets()
+
+
+# ---------------------------------------------------------------------------
+# Genetic algorithm (Sec. 2): B-spline genome and the generation operators
+# ---------------------------------------------------------------------------
+
+def bspline_point(Q, degree, u):
+    """Point of the clamped uniform B-spline with control points Q [M, 2] at u."""
+    Q = _f64(Q).reshape(-1)
+    out = np.zeros(2)
+    lib().oracle_bspline_point(Q.size // 2, int(degree), Q, float(u), out)
+    return out
+
+
+def bspline_param(k, N):
+    return lib().oracle_bspline_param(int(k), int(N))
+
+
+def bspline_nodes(template, gene_map, genome, degree, N):
+    """Contour nodes [B, N+1, 2] of the genomes [B, G]."""
+    template = _f64(template).reshape(-1)
+    genome = _f64(np.atleast_2d(genome))
+    B, G = genome.shape
+    gm = np.ascontiguousarray(gene_map, dtype=np.int32)
+    xy = np.zeros(B * 2 * (N + 1))
+    lib().oracle_bspline_nodes(B, int(N), template.size // 2, int(degree), G, template, gm, genome.reshape(-1), xy)
+    return xy.reshape(B, N + 1, 2)
+
+
+def ga_uniforms_per_generation(B, k):
+    """Uniforms one generation consumes: (B/2)(4k - 1) for the pairs, 3 per child."""
+    return (B // 2) * (4 * k - 1) + 3 * B
+
+
+def ga_init(lo, hi, u):
+    lo, hi = _f64(lo), _f64(hi)
+    u = _f64(np.atleast_2d(u))
+    B, G = u.shape
+    out = np.zeros(B * G)
+    lib().oracle_ga_init(B, G, lo, hi, u.reshape(-1), out)
+    return out.reshape(B, G)
+
+
+def ga_fitness(alpha_off, ld, info):
+    alpha_off = np.ascontiguousarray(alpha_off, dtype=np.int32)
+    B = alpha_off.size - 1
+    out = np.zeros(B)
+    lib().oracle_ga_fitness(B, alpha_off, _f64(ld), np.ascontiguousarray(info, dtype=np.int32), out)
+    return out
+
+
+def ga_step(genome, fitness, u, k, p_sel, p_mut, sigma, lo, hi):
+    """Next generation [B, G] and its trace [B, 4] (parents, cut, mutated gene)."""
+    genome = _f64(genome)
+    B, G = genome.shape
+    u = _f64(u).reshape(-1)
+    if u.size < ga_uniforms_per_generation(B, k):
+        raise ValueError("too few uniforms for one generation")
+    out = np.zeros(B * G)
+    trace = np.zeros(4 * B, dtype=np.int32)
+    lib().oracle_ga_step(B, G, int(k), float(p_sel), float(p_mut), float(sigma), _f64(lo), _f64(hi),
+                         _f64(fitness), genome.reshape(-1), u, out, trace)
+    return out.reshape(B, G), trace.reshape(B, 4)

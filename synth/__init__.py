@@ -174,3 +174,48 @@ def joukowski_batch(seed: int, B: int, n_panels) -> tuple[np.ndarray, np.ndarray
         mu = complex(-rng.uniform(0.01, 0.06), rng.uniform(0.0, 0.06))
         nodes.append(joukowski_nodes(int(ns[b]), 0.25, mu))
     return pack_nodes(nodes)
+
+
+# ---------------------------------------------------------------------------
+# Genetic-algorithm inputs: the genome's control-point template and bounds,
+# and the uniform random numbers each generation consumes.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class GaProblem:
+    """Control-point template [M, 2] of a closed contour (first = last = the
+    trailing edge (1, 0)), the coordinates the genes set (indices into the
+    flattened template) and per-gene bounds."""
+
+    template: np.ndarray
+    gene_map: np.ndarray
+    lo: np.ndarray
+    hi: np.ndarray
+    degree: int = 3
+
+    @property
+    def G(self) -> int:
+        return int(self.gene_map.size)
+
+
+def ga_problem(m: int = 6, degree: int = 3) -> GaProblem:
+    """m control points per surface at fixed cosine-spaced abscissae (the last
+    of each at x = 0, so the leading edge has a vertical tangent); the genes
+    are their ordinates: upper surface in [0.01, 0.16], lower in
+    [-0.10, -0.01]."""
+    X = 0.5 * (1.0 + np.cos(np.pi * np.arange(1, m + 1) / m))
+    X[-1] = 0.0
+    M = 2 * m + 2
+    T = np.zeros((M, 2))
+    T[0] = T[-1] = (1.0, 0.0)
+    T[1:m + 1, 0] = X
+    T[m + 1:2 * m + 1, 0] = X[::-1]
+    gene_map = np.array([2 * i + 1 for i in range(1, 2 * m + 1)], dtype=np.int32)
+    lo = np.concatenate([np.full(m, 0.01), np.full(m, -0.10)])
+    hi = np.concatenate([np.full(m, 0.16), np.full(m, -0.01)])
+    return GaProblem(T, gene_map, lo, hi, degree)
+
+
+def ga_uniforms(seed: int, count: int, rows: int = 1) -> np.ndarray:
+    """Uniform [0, 1) draws, [rows, count]."""
+    return np.random.default_rng(seed).random((rows, count))
