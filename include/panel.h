@@ -281,6 +281,90 @@ panel_status panel_naca4(int32_t B, const int32_t *node_off, int32_t closed_te,
 panel_status panel_naca4_vjp(int32_t B, const int32_t *node_off, int32_t closed_te,
                              const double *mpt, const double *dxy, double *dmpt, void *stream);
 
+/* ---- Genetic algorithm (Sec. 2, the shape optimisation) -------------------
+ * The genome is the list of B-spline coefficients of the contour, ordered
+ * from the trailing edge over the upper surface to the trailing edge on the
+ * lower surface; a generation evaluates every individual with the panel
+ * method (fitness: lift-to-drag ratio with the viscous correction), selects
+ * parents by tournament, recombines them by one-point crossover and mutates
+ * children with some probability.  The paper does not fix the spline, the
+ * bounds or the operator parameters; the readings here: clamped B-spline
+ * of degree d, uniform interior knots; tournament draws with replacement;
+ * crossover position in 1..G-1; a mutation moves one gene by a uniform
+ * amount of at most sigma (hi - lo) and clamps it; no elitism.  Random
+ * numbers are inputs: DEVICE arrays of uniforms in [0, 1).
+ * Genomes are B x G doubles, row-major.                                    */
+#define PANEL_GA_MAX_GENES 64
+#define PANEL_GA_MAX_CTRL 64
+#define PANEL_GA_MAX_DEGREE 7
+#define PANEL_GA_MAX_TOURNAMENT 16
+
+/* Contour nodes of B genomes: control points Q (h_template, M points, x y
+ * interleaved) with genome[b G + g] written to coordinate h_gene_map[g] of
+ * Q; the clamped B-spline of degree d on Q (knots t_j = 0 for j <= d,
+ * (j - d)/(M - d) between, 1 for j >= M) is sampled at
+ *   u_k = (1 - cos(2 pi k / N)) / 4  (k <= N/2),  u_k = 1 - u_{N-k} above,
+ * clustering nodes at both trailing-edge ends and at the middle of the
+ * parameter range.  The first and last template points must coincide (the
+ * trailing edge) and carry no gene, so node N equals node 0 exactly.
+ *   N           even, PANEL_NMIN..PANEL_NMAX; xy gets B (N + 1) nodes, the
+ *               layout of a plan with node_offsets b (N + 1)
+ *   h_template  HOST, 2M finite doubles, degree + 1 <= M <= PANEL_GA_MAX_CTRL
+ *   h_gene_map  HOST, G distinct indices in [2, 2M - 2), G <= PANEL_GA_MAX_GENES
+ *   genome      DEVICE B x G;  xy  DEVICE 2 B (N + 1), written           */
+panel_status panel_bspline_nodes(int32_t B, int32_t N, int32_t M, int32_t degree, const double *h_template,
+                                 int32_t G, const int32_t *h_gene_map, const double *genome, double *xy,
+                                 void *stream);
+
+/* Random initial genomes: genome[b G + g] = lo_g + (hi_g - lo_g) u[b G + g].
+ *   h_lo, h_hi  HOST, G finite bounds with lo <= hi;  u DEVICE B x G      */
+panel_status panel_ga_init(int32_t B, int32_t G, const double *h_lo, const double *h_hi, const double *u,
+                           double *genome, void *stream);
+
+/* Fitness of each airfoil of a plan: the mean over its angles of ld (the
+ * output of panel_thwaites), or -infinity when info[b] != 0 (the output of
+ * panel_factor_solve) or one of its ld values is not finite.
+ *   ld DEVICE alpha_offsets[B];  info DEVICE int32 B;  fitness DEVICE B   */
+panel_status panel_ga_fitness(const panel_plan *plan, const void *ws, const double *ld, const int32_t *info,
+                              double *fitness, void *stream);
+
+/* Number of uniforms one generation of panel_ga_step reads:
+ * (B/2)(4k - 1) + 3B.                                                      */
+panel_status panel_ga_uniform_count(int32_t B, int32_t k, int64_t *count);
+
+/* One generation: B/2 child pairs, then each child's mutation trial.  For
+ * pair q, u[q (4k-1) ...] holds tournament 1 (k draws, index
+ * min(B-1, floor(U B)); k-1 rank trials: the rank taken is the first
+ * r < k-1 whose trial is < p_sel, else k-1, ranks counting fitness
+ * descending, equal fitness in draw order), tournament 2 (the same) and the
+ * crossover draw c = 1 + min(G-2, floor(U (G-1))); child 2q takes genes
+ * [0, c) from the first parent and [c, G) from the second, child 2q+1 the
+ * reverse.  For child i, u[(B/2)(4k-1) + 3i ...] = (X, Y, Z): if X < p_mut,
+ * gene j = min(G-1, floor(Y G)) becomes
+ * clamp(gene + sigma (hi_j - lo_j)(2Z - 1), lo_j, hi_j).
+ *   B even >= 2;  2 <= G <= PANEL_GA_MAX_GENES;  1 <= k <= PANEL_GA_MAX_TOURNAMENT
+ *   p_sel in (0, 1];  p_mut in [0, 1];  sigma finite >= 0
+ *   fitness     DEVICE B, no NaN (-infinity marks an unusable individual)
+ *   genome_in / genome_out  DEVICE B x G, distinct buffers
+ *   u           DEVICE, panel_ga_uniform_count values
+ *   trace       DEVICE int32 4B or NULL: per child, first parent, second
+ *               parent, crossover position, mutated gene (-1 if none)    */
+panel_status panel_ga_step(int32_t B, int32_t G, int32_t k, double p_sel, double p_mut, double sigma,
+                           const double *h_lo, const double *h_hi, const double *fitness,
+                           const double *genome_in, const double *u, double *genome_out, int32_t *trace,
+                           void *stream);
+
+/* History of the run, kept on the device: the generation's best individual
+ * (highest fitness, lowest index among equals) is written to slot *counter
+ * of hist_fit / hist_idx when *counter < max_gen; if it beats *best_fit it
+ * replaces *best_fit and its genome is copied to best_genome; *counter then
+ * advances.  The caller sets *counter = 0 and *best_fit = -infinity first.
+ *   counter DEVICE int32[1];  hist_fit DEVICE max_gen;  hist_idx DEVICE
+ *   int32 max_gen;  best_fit DEVICE [1];  best_genome DEVICE G            */
+panel_status panel_ga_record(int32_t B, int32_t G, const double *fitness, const double *genome,
+                             int32_t *counter, int32_t max_gen, double *hist_fit, int32_t *hist_idx,
+                             double *best_fit, double *best_genome, void *stream);
+
 /* Largest workspace panel_solve_noalloc can hold (bytes of the library's
  * static device scratch array, one per GPU, held until the process ends). */
 #define PANEL_NOALLOC_MAX_BYTES ((size_t)256 << 20)

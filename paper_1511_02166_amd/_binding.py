@@ -14,6 +14,7 @@ PANEL_FP64, PANEL_FP32_REFINE = 0, 1
 PANEL_STREAM_FUNCTION, PANEL_HESS_SMITH = 0, 1
 PANEL_NMAX, PANEL_NMIN, PANEL_KMAX = 1024, 4, 16
 PANEL_NOALLOC_MAX_BYTES = 256 << 20
+PANEL_GA_MAX_GENES, PANEL_GA_MAX_CTRL, PANEL_GA_MAX_DEGREE, PANEL_GA_MAX_TOURNAMENT = 64, 64, 7, 16
 
 _lib = None
 
@@ -65,6 +66,12 @@ def load_library():
     L.panel_naca4_vjp.argtypes = [i32, vp, i32, vp, vp, vp, vp]
     L.panel_math_eval.argtypes = [i32, vp, vp, vp, vp, vp]
     L.panel_solve_noalloc.argtypes = [vp, vp, vp, vp, f64, f64, i32, vp, vp, vp, vp, vp, vp]
+    L.panel_bspline_nodes.argtypes = [i32, i32, i32, i32, vp, i32, vp, vp, vp, vp]
+    L.panel_ga_init.argtypes = [i32, i32, vp, vp, vp, vp, vp]
+    L.panel_ga_fitness.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.panel_ga_uniform_count.argtypes = [i32, i32, C.POINTER(C.c_int64)]
+    L.panel_ga_step.argtypes = [i32, i32, i32, f64, f64, f64, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.panel_ga_record.argtypes = [i32, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp]
     L.panel_status_str.argtypes = [i32]
     L.panel_status_str.restype = C.c_char_p
     L.panel_last_error.argtypes = []
@@ -74,7 +81,8 @@ def load_library():
                  "panel_workspace_size", "panel_workspace_init",
                  "panel_workspace_layout", "panel_assemble",
                  "panel_factor_solve", "panel_forces", "panel_adjoint", "panel_naca4", "panel_thwaites",
-                 "panel_naca4_vjp", "panel_math_eval", "panel_solve_noalloc"):
+                 "panel_naca4_vjp", "panel_math_eval", "panel_solve_noalloc", "panel_bspline_nodes", "panel_ga_init",
+                 "panel_ga_fitness", "panel_ga_uniform_count", "panel_ga_step", "panel_ga_record"):
         getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -287,3 +295,74 @@ def panel_math_eval(x, y, log_out, atan2_out, stream=None):
     _check(load_library().panel_math_eval(int(x.numel()), _ptr(x, d, "x"), _ptr(y, d, "y", True),
                                           _ptr(log_out, d, "log_out", True),
                                           _ptr(atan2_out, d, "atan2_out", True), _stream(stream)))
+
+
+# ---- genetic algorithm -----------------------------------------------------------
+
+def _host_f64(a, name):
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _host_i32(a, name):
+    a = np.ascontiguousarray(a, dtype=np.int32).reshape(-1)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def panel_bspline_nodes(B, N, template, degree, gene_map, genome, xy, stream=None):
+    """template: host [M, 2]; gene_map: host int [G]; genome, xy: device."""
+    import torch
+    t, tp = _host_f64(template, "template")
+    gm, gp = _host_i32(gene_map, "gene_map")
+    _check(load_library().panel_bspline_nodes(int(B), int(N), t.size // 2, int(degree), tp, gm.size, gp,
+                                              _ptr(genome, torch.float64, "genome", allow_none=gm.size == 0),
+                                              _ptr(xy, torch.float64, "xy"), _stream(stream)))
+
+
+def panel_ga_init(B, G, lo, hi, u, genome, stream=None):
+    import torch
+    lo_, lp = _host_f64(lo, "lo")
+    hi_, hp = _host_f64(hi, "hi")
+    if lo_.size != G or hi_.size != G:
+        raise ValueError("lo and hi need one value per gene")
+    _check(load_library().panel_ga_init(int(B), int(G), lp, hp, _ptr(u, torch.float64, "u"),
+                                        _ptr(genome, torch.float64, "genome"), _stream(stream)))
+
+
+def panel_ga_fitness(plan: Plan, ws, ld, info, fitness, stream=None):
+    import torch
+    _check(load_library().panel_ga_fitness(plan.handle, _ptr(ws, torch.uint8, "ws"), _ptr(ld, torch.float64, "ld"),
+                                           _ptr(info, torch.int32, "info"), _ptr(fitness, torch.float64, "fitness"),
+                                           _stream(stream)))
+
+
+def panel_ga_uniform_count(B, k) -> int:
+    n = C.c_int64()
+    _check(load_library().panel_ga_uniform_count(int(B), int(k), C.byref(n)))
+    return int(n.value)
+
+
+def panel_ga_step(B, G, k, p_sel, p_mut, sigma, lo, hi, fitness, genome_in, u, genome_out, trace=None,
+                  stream=None):
+    import torch
+    lo_, lp = _host_f64(lo, "lo")
+    hi_, hp = _host_f64(hi, "hi")
+    if lo_.size != G or hi_.size != G:
+        raise ValueError("lo and hi need one value per gene")
+    _check(load_library().panel_ga_step(int(B), int(G), int(k), float(p_sel), float(p_mut), float(sigma), lp, hp,
+                                        _ptr(fitness, torch.float64, "fitness"),
+                                        _ptr(genome_in, torch.float64, "genome_in"), _ptr(u, torch.float64, "u"),
+                                        _ptr(genome_out, torch.float64, "genome_out"),
+                                        _ptr(trace, torch.int32, "trace", allow_none=True), _stream(stream)))
+
+
+def panel_ga_record(B, G, fitness, genome, counter, max_gen, hist_fit, hist_idx, best_fit, best_genome,
+                    stream=None):
+    import torch
+    d = torch.float64
+    _check(load_library().panel_ga_record(int(B), int(G), _ptr(fitness, d, "fitness"), _ptr(genome, d, "genome"),
+                                          _ptr(counter, torch.int32, "counter"), int(max_gen),
+                                          _ptr(hist_fit, d, "hist_fit", allow_none=max_gen == 0),
+                                          _ptr(hist_idx, torch.int32, "hist_idx", allow_none=max_gen == 0),
+                                          _ptr(best_fit, d, "best_fit"), _ptr(best_genome, d, "best_genome"),
+                                          _stream(stream)))

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libpanel.so")
 ARCH = os.environ.get("PANEL_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["panel_abi.cpp", "geometry.hip", "assemble.hip", "assemble_hs.hip", "lu.hip", "lu_wave.hip", "forces.hip",
-           "adjoint.hip", "adjoint_wave.hip", "viscous.hip", "mathcheck.hip"]
+           "adjoint.hip", "adjoint_wave.hip", "viscous.hip", "ga.hip", "mathcheck.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}",

@@ -482,6 +482,128 @@ panel_status panel_naca4_vjp(int32_t B, const int32_t *node_off, int32_t closed_
     return check_hip(e, "naca4 vjp launch");
 }
 
+// ---- genetic algorithm ---------------------------------------------------------
+
+static panel_status ga_bounds(int32_t G, const double *lo, const double *hi, GaOps *o) {
+    if (!lo || !hi) return fail(PANEL_EINVAL, "NULL bounds");
+    for (int g = 0; g < G; ++g) {
+        if (!(std::isfinite(lo[g]) && std::isfinite(hi[g]) && lo[g] <= hi[g]))
+            return fail(PANEL_EINVAL, "bounds must be finite with lo <= hi");
+        o->lo[g] = lo[g];
+        o->hi[g] = hi[g];
+    }
+    return ok();
+}
+
+panel_status panel_bspline_nodes(int32_t B, int32_t N, int32_t M, int32_t degree, const double *h_template,
+                                 int32_t G, const int32_t *h_gene_map, const double *genome, double *xy,
+                                 void *stream) {
+    if (B < 1) return fail(PANEL_EINVAL, "B must be >= 1");
+    if (N < PANEL_NMIN || N > PANEL_NMAX || (N & 1)) return fail(PANEL_EINVAL, "N must be even, NMIN..NMAX");
+    if (degree < 1 || degree > PANEL_GA_MAX_DEGREE) return fail(PANEL_EINVAL, "degree must be 1..PANEL_GA_MAX_DEGREE");
+    if (M < degree + 1 || M > PANEL_GA_MAX_CTRL) return fail(PANEL_EINVAL, "need degree + 1 <= M <= PANEL_GA_MAX_CTRL");
+    if (G < 0 || G > PANEL_GA_MAX_GENES) return fail(PANEL_EINVAL, "G must be 0..PANEL_GA_MAX_GENES");
+    if (!h_template || (G > 0 && (!h_gene_map || !genome)) || !xy) return fail(PANEL_EINVAL, "NULL argument");
+    if ((genome && !aligned8(genome)) || !aligned8(xy)) return fail(PANEL_EINVAL, "arrays must be 8-byte aligned");
+    GaContour c{};
+    c.M = M;
+    c.degree = degree;
+    c.G = G;
+    for (int i = 0; i < 2 * M; ++i) {
+        if (!std::isfinite(h_template[i])) return fail(PANEL_EINVAL, "template must be finite");
+        c.tmpl[i] = h_template[i];
+    }
+    if (h_template[0] != h_template[2 * M - 2] || h_template[1] != h_template[2 * M - 1])
+        return fail(PANEL_EINVAL, "first and last control points must coincide (the trailing edge)");
+    bool used[2 * PANEL_GA_MAX_CTRL] = {};
+    for (int g = 0; g < G; ++g) {
+        const int32_t t = h_gene_map[g];
+        if (t < 2 || t >= 2 * M - 2) return fail(PANEL_EINVAL, "gene_map entries must lie in [2, 2M - 2)");
+        if (used[t]) return fail(PANEL_EINVAL, "gene_map entries must be distinct");
+        used[t] = true;
+        c.gene_map[g] = t;
+    }
+    hipError_t e = launch_bspline_nodes(c, B, N, genome, xy, static_cast<hipStream_t>(stream));
+    return check_hip(e, "B-spline nodes launch");
+}
+
+panel_status panel_ga_init(int32_t B, int32_t G, const double *h_lo, const double *h_hi, const double *u,
+                           double *genome, void *stream) {
+    if (B < 1) return fail(PANEL_EINVAL, "B must be >= 1");
+    if (G < 1 || G > PANEL_GA_MAX_GENES) return fail(PANEL_EINVAL, "G must be 1..PANEL_GA_MAX_GENES");
+    if (!u || !genome) return fail(PANEL_EINVAL, "NULL argument");
+    if (!aligned8(u) || !aligned8(genome)) return fail(PANEL_EINVAL, "arrays must be 8-byte aligned");
+    GaOps o{};
+    o.G = G;
+    panel_status st = ga_bounds(G, h_lo, h_hi, &o);
+    if (st != PANEL_OK) return st;
+    hipError_t e = launch_ga_init(o, B, u, genome, static_cast<hipStream_t>(stream));
+    return check_hip(e, "GA init launch");
+}
+
+panel_status panel_ga_fitness(const panel_plan *plan, const void *ws, const double *ld, const int32_t *info,
+                              double *fitness, void *stream) {
+    if (!plan || !ws || !ld || !info || !fitness) return fail(PANEL_EINVAL, "NULL argument");
+    if (!aligned8(ld) || !aligned8(fitness) || (reinterpret_cast<uintptr_t>(info) & 3u))
+        return fail(PANEL_EINVAL, "arrays must be aligned (8 bytes; info 4 bytes)");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(PANEL_EINVAL, "workspace must be 256-byte aligned");
+    WsView v = ws_view(const_cast<void *>(ws), plan->layout);
+    hipError_t e = launch_ga_fitness(v, plan->B, ld, info, fitness, static_cast<hipStream_t>(stream));
+    return check_hip(e, "GA fitness launch");
+}
+
+panel_status panel_ga_uniform_count(int32_t B, int32_t k, int64_t *count) {
+    if (!count) return fail(PANEL_EINVAL, "NULL argument");
+    if (B < 2 || (B & 1)) return fail(PANEL_EINVAL, "B must be even and >= 2");
+    if (k < 1 || k > PANEL_GA_MAX_TOURNAMENT) return fail(PANEL_EINVAL, "k must be 1..PANEL_GA_MAX_TOURNAMENT");
+    *count = (int64_t)(B / 2) * (4 * k - 1) + 3 * (int64_t)B;
+    return ok();
+}
+
+panel_status panel_ga_step(int32_t B, int32_t G, int32_t k, double p_sel, double p_mut, double sigma,
+                           const double *h_lo, const double *h_hi, const double *fitness,
+                           const double *genome_in, const double *u, double *genome_out, int32_t *trace,
+                           void *stream) {
+    if (B < 2 || (B & 1)) return fail(PANEL_EINVAL, "B must be even and >= 2");
+    if (G < 2 || G > PANEL_GA_MAX_GENES) return fail(PANEL_EINVAL, "G must be 2..PANEL_GA_MAX_GENES");
+    if (k < 1 || k > PANEL_GA_MAX_TOURNAMENT) return fail(PANEL_EINVAL, "k must be 1..PANEL_GA_MAX_TOURNAMENT");
+    if (!(p_sel > 0.0 && p_sel <= 1.0)) return fail(PANEL_EINVAL, "p_sel must be in (0, 1]");
+    if (!(p_mut >= 0.0 && p_mut <= 1.0)) return fail(PANEL_EINVAL, "p_mut must be in [0, 1]");
+    if (!(std::isfinite(sigma) && sigma >= 0.0)) return fail(PANEL_EINVAL, "sigma must be finite and >= 0");
+    if (!fitness || !genome_in || !u || !genome_out) return fail(PANEL_EINVAL, "NULL argument");
+    if (genome_in == genome_out) return fail(PANEL_EINVAL, "genome_in and genome_out must differ");
+    if (!aligned8(fitness) || !aligned8(genome_in) || !aligned8(u) || !aligned8(genome_out) ||
+        (reinterpret_cast<uintptr_t>(trace) & 3u))
+        return fail(PANEL_EINVAL, "arrays must be aligned (8 bytes; trace 4 bytes)");
+    GaOps o{};
+    o.G = G;
+    o.k = k;
+    o.p_sel = p_sel;
+    o.p_mut = p_mut;
+    o.sigma = sigma;
+    panel_status st = ga_bounds(G, h_lo, h_hi, &o);
+    if (st != PANEL_OK) return st;
+    hipError_t e = launch_ga_step(o, B, fitness, genome_in, u, genome_out, trace, static_cast<hipStream_t>(stream));
+    return check_hip(e, "GA step launch");
+}
+
+panel_status panel_ga_record(int32_t B, int32_t G, const double *fitness, const double *genome,
+                             int32_t *counter, int32_t max_gen, double *hist_fit, int32_t *hist_idx,
+                             double *best_fit, double *best_genome, void *stream) {
+    if (B < 1) return fail(PANEL_EINVAL, "B must be >= 1");
+    if (G < 1 || G > PANEL_GA_MAX_GENES) return fail(PANEL_EINVAL, "G must be 1..PANEL_GA_MAX_GENES");
+    if (max_gen < 0) return fail(PANEL_EINVAL, "max_gen must be >= 0");
+    if (!fitness || !genome || !counter || !best_fit || !best_genome || (max_gen > 0 && (!hist_fit || !hist_idx)))
+        return fail(PANEL_EINVAL, "NULL argument");
+    if (!aligned8(fitness) || !aligned8(genome) || !aligned8(best_fit) || !aligned8(best_genome) ||
+        (hist_fit && !aligned8(hist_fit)) || (reinterpret_cast<uintptr_t>(counter) & 3u) ||
+        (reinterpret_cast<uintptr_t>(hist_idx) & 3u))
+        return fail(PANEL_EINVAL, "arrays must be aligned (8 bytes; int32 4 bytes)");
+    hipError_t e = launch_ga_record(B, G, fitness, genome, counter, max_gen, hist_fit, hist_idx, best_fit,
+                                    best_genome, static_cast<hipStream_t>(stream));
+    return check_hip(e, "GA record launch");
+}
+
 panel_status panel_math_eval(int32_t n, const double *x, const double *y, double *log_out,
                              double *atan2_out, void *stream) {
     if (n < 0) return fail(PANEL_EINVAL, "n must be >= 0");

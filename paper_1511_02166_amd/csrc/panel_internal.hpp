@@ -136,4 +136,27 @@ hipError_t launch_adjoint_wave(const WsView &v, int32_t first, int32_t count, in
 hipError_t launch_adjoint_hs(const WsView &v, int32_t B, int32_t mixed, const double *xy, const double *dcl,
                              const double *dcp, double *dxy, int32_t *info, hipStream_t stream);
 
+// Genetic algorithm (ga.hip).  Small tables travel by value as kernel
+// arguments.
+struct GaContour {
+    int32_t M, degree, G;
+    int32_t gene_map[PANEL_GA_MAX_GENES];
+    double tmpl[2 * PANEL_GA_MAX_CTRL];
+};
+struct GaOps {
+    int32_t G, k;
+    double p_sel, p_mut, sigma;
+    double lo[PANEL_GA_MAX_GENES], hi[PANEL_GA_MAX_GENES];
+};
+hipError_t launch_bspline_nodes(const GaContour &c, int32_t B, int32_t N, const double *genome, double *xy,
+                                hipStream_t stream);
+hipError_t launch_ga_init(const GaOps &o, int32_t B, const double *u, double *genome, hipStream_t stream);
+hipError_t launch_ga_fitness(const WsView &v, int32_t B, const double *ld, const int32_t *info, double *fitness,
+                             hipStream_t stream);
+hipError_t launch_ga_step(const GaOps &o, int32_t B, const double *fitness, const double *gin, const double *u,
+                          double *gout, int32_t *trace, hipStream_t stream);
+hipError_t launch_ga_record(int32_t B, int32_t G, const double *fitness, const double *genome, int32_t *counter,
+                            int32_t max_gen, double *hist_fit, int32_t *hist_idx, double *best_fit,
+                            double *best_genome, hipStream_t stream);
+
 }  // namespace panel

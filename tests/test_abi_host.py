@@ -183,3 +183,53 @@ def test_formulation_switch_and_workspace(lib):
     d = (C.c_int64 * 9)()
     assert lib.panel_workspace_layout(h, 1, d) == 0 and d[8] > d[0]
     lib.panel_plan_destroy(h)
+
+
+def test_ga_entry_points_validate_before_any_hip_call(lib):
+    # B-spline contours: closure, gene map, sizes; GA step: population,
+    # tournament size, probabilities, buffers; the uniform count
+    import paper_1511_02166_amd as P
+    EINVAL = P._binding.PANEL_EINVAL
+    fake = C.c_void_p(0x100000)
+    T = np.array([[1.0, 0.0], [0.5, 0.1], [0.0, 0.0], [0.5, -0.1], [1.0, 0.0]])
+    tp = T.ctypes.data_as(C.c_void_p)
+    gm = np.array([3, 7], dtype=np.int32)
+    gp = gm.ctypes.data_as(C.c_void_p)
+    assert lib.panel_bspline_nodes(4, 64, 5, 3, tp, 2, gp, fake, C.c_void_p(0x100004), None) == EINVAL  # unaligned
+    assert lib.panel_bspline_nodes(4, 63, 5, 3, tp, 2, gp, fake, fake, None) == EINVAL    # odd N
+    assert lib.panel_bspline_nodes(4, 64, 5, 5, tp, 2, gp, fake, fake, None) == EINVAL    # M < degree + 1
+    assert lib.panel_bspline_nodes(4, 64, 5, 8, tp, 2, gp, fake, fake, None) == EINVAL    # degree > max
+    open_T = T.copy()
+    open_T[-1, 1] = 1e-3
+    assert lib.panel_bspline_nodes(4, 64, 5, 3, open_T.ctypes.data_as(C.c_void_p), 2, gp, fake, fake,
+                                   None) == EINVAL                                     # not closed
+    for bad in ([1, 7], [3, 8], [3, 3]):   # gene on the trailing edge, out of range, repeated
+        b = np.array(bad, dtype=np.int32)
+        assert lib.panel_bspline_nodes(4, 64, 5, 3, tp, 2, b.ctypes.data_as(C.c_void_p), fake, fake,
+                                       None) == EINVAL, bad
+    n = C.c_int64()
+    assert lib.panel_ga_uniform_count(2048, 4, C.byref(n)) == 0 and n.value == 1024 * 15 + 3 * 2048
+    assert lib.panel_ga_uniform_count(7, 4, C.byref(n)) == EINVAL
+    assert lib.panel_ga_uniform_count(8, 17, C.byref(n)) == EINVAL
+    lo = np.zeros(2)
+    hi = np.ones(2)
+    lp, hp = lo.ctypes.data_as(C.c_void_p), hi.ctypes.data_as(C.c_void_p)
+    f2 = C.c_void_p(0x200000)
+    ok_args = dict(B=8, G=2, k=3, p_sel=0.7, p_mut=0.1, sigma=0.1)
+
+    def step(**kw):
+        a = dict(ok_args, **kw)
+        gin = kw.get("gin", fake)
+        return lib.panel_ga_step(a["B"], a["G"], a["k"], C.c_double(a["p_sel"]), C.c_double(a["p_mut"]),
+                                 C.c_double(a["sigma"]), lp, hp, fake, gin, fake, f2, None, None)
+    assert step(B=7) == EINVAL and step(B=0) == EINVAL
+    assert step(G=1) == EINVAL and step(G=65) == EINVAL
+    assert step(k=0) == EINVAL and step(k=17) == EINVAL
+    assert step(p_sel=0.0) == EINVAL and step(p_sel=1.5) == EINVAL
+    assert step(p_mut=-0.1) == EINVAL and step(sigma=float("nan")) == EINVAL
+    assert step(gin=f2) == EINVAL   # in place
+    hi_bad = np.array([1.0, -1.0])
+    assert lib.panel_ga_step(8, 2, 3, C.c_double(0.7), C.c_double(0.1), C.c_double(0.1), lp,
+                             hi_bad.ctypes.data_as(C.c_void_p), fake, fake, fake, f2, None, None) == EINVAL
+    assert lib.panel_ga_init(8, 2, lp, hi_bad.ctypes.data_as(C.c_void_p), fake, f2, None) == EINVAL
+    assert lib.panel_ga_record(8, 2, fake, fake, fake, 5, None, None, fake, fake, None) == EINVAL
