@@ -14,7 +14,10 @@ Prints ONE JSON line.  ``value`` is the FP64 solves/s on the GA-population
 batch (2048 seeded NACA 4-digit airfoils, 256 panels, 257x257 systems);
 the FP32+refinement rate, the adjoint rate (1024 airfoils at 6 degrees),
 per-kernel times, the roofline of every hot kernel, the uneven and
-large-panel batches and the CPU oracle baseline ride along.
+large-panel batches, the Hess-Smith formulation on the same batch, one
+generation of the on-device genetic algorithm, the paper's hybrid scheme
+(device assembly, host LAPACK in slices) as an ablation and the CPU oracle
+baseline ride along.
 """
 from __future__ import annotations
 
@@ -64,6 +67,8 @@ def _args():
                     help="airfoils in the all-core oracle sample (default: the whole batch)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip the uneven and large-panel batches")
+    ap.add_argument("--no-ga", action="store_true", help="skip the on-device genetic-algorithm generation")
+    ap.add_argument("--no-hybrid", action="store_true", help="skip the host-LAPACK hybrid ablation")
     ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of a graph replay")
     ap.add_argument("--wave-limit", type=int, default=None,
                     help="largest system order for the one-wavefront LU (0 = workgroup LU only); "
@@ -291,6 +296,98 @@ def main():
             del t64, t32
             torch.cuda.empty_cache()
 
+    # the Hess-Smith formulation on the same batch and nodes
+    if not a.no_side and a.batch is None:
+        hs = {}
+        for tag, prec in (("fp64", P.PANEL_FP64), ("fp32_refine", P.PANEL_FP32_REFINE)):
+            sh = P.PanelSolver(noff, aoff, prec, formulation=P.PANEL_HESS_SMITH)
+            q = replay(sh, xy, alpha, max(3, a.steps // 2), 1, use_graph)
+            hs[f"{tag}_ms_per_step"] = q["ms_per_step"]
+            hs[f"{tag}_solves_per_s"] = n_solves / (q["ms_per_step"] * 1e-3)
+            del sh
+        side[f"{w.name}_hess_smith"] = hs
+        torch.cuda.empty_cache()
+
+    # one generation of the on-device genetic algorithm: B-spline contours of
+    # 2048 genomes (N=256), the FP64 panel solve at zero incidence, Thwaites'
+    # correction (Re = 1e6), fitness, history and the next generation
+    ga = None
+    if not a.no_ga and a.batch is None:
+        prob = synth.ga_problem(6)
+        opt = P.GeneticOptimizer(2048, 256, prob.template, prob.gene_map, prob.lo, prob.hi, prob.degree,
+                                 alpha=(0.0,), re=1e6, seed=1)
+        opt.initialize()
+        for _ in range(a.warmup):
+            opt.generation()
+        torch.cuda.synchronize()
+        n_ev = 6
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ev)] for _ in range(a.steps)]
+        so = opt.solver
+        for i in range(a.steps):
+            e = evs[i]
+            e[0].record(stream)
+            opt.contours()
+            e[1].record(stream)
+            so.step(opt.xy, opt.alpha)
+            e[2].record(stream)
+            P.panel_thwaites(so.plan, so.ws, so.gamma, so.cl, opt.re, opt.cd, opt.ld, opt.sep)
+            e[3].record(stream)
+            P.panel_ga_fitness(so.plan, so.ws, opt.ld, so.info, opt.fitness)
+            opt.record()
+            e[4].record(stream)
+            opt.breed()
+            e[5].record(stream)
+        torch.cuda.synchronize()
+        part = lambda i: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs]))
+        opt.capture()
+        for _ in range(a.warmup):
+            opt._graph.replay()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(a.steps):
+            opt._graph.replay()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / a.steps
+        hist = opt.history()
+        ga = {"workload": "2048 B-spline genomes (12 genes, cubic, 14 control points), N=256, alpha=0, Re=1e6, "
+                          "tournament k=4 p=0.75, mutation 0.2 x 0.1",
+              "ms_per_generation": ms, "generations_per_s": 1e3 / ms, "solves_per_s": opt.pop / (ms * 1e-3),
+              "timing": "hip graph replay of one generation",
+              "eager_breakdown_ms": {"contours": part(0), "panel_solve": part(1), "thwaites": part(2),
+                                     "fitness_and_history": part(3), "random_draws_and_step": part(4)},
+              "generations_run": int(opt.counter.item()), "best_fitness": float(opt.best_fit.item()),
+              "best_per_generation_first_last": [float(hist[0]), float(hist[-1])]}
+        del opt, so
+        torch.cuda.empty_cache()
+
+    # the paper's hybrid scheme as an ablation: device assembly, systems
+    # copied to pinned host memory slice by slice, LAPACK solves on the host
+    # cores (CPU_SHARE threads) overlapping the next slice's assembly and copy
+    hyb = None
+    if not a.no_hybrid and a.batch is None:
+        from paper_1511_02166_amd.hybrid import HybridSolver
+        cpu_thr = max(1, min(len(os.sched_getaffinity(0)), CPU_SHARE))
+        hyb = {"workload": f"{w.name}, FP64 systems, {cpu_thr} host threads", "slices": {}}
+        ref_cl = s64.cl.cpu().numpy()
+        for ns in (1, 5, 10, 20):
+            h = HybridSolver(noff, aoff, ns, threads=cpu_thr)
+            h.step(xy, alpha)   # warm-up
+            runs = [h.step(xy, alpha) for _ in range(2)]
+            h.close()
+            cl_h, t = min(runs, key=lambda r: r[1]["W"])
+            t = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in t.items()}
+            t["solves_per_s"] = n_solves / t["W"]
+            t["cl_err_vs_device"] = float(np.max(np.abs(cl_h - ref_cl) / np.maximum(1.0, np.abs(ref_cl))))
+            hyb["slices"][str(ns)] = t
+            del h
+        hyb["all_device_ms_per_step"] = r64["ms_per_step"]
+        best = min(hyb["slices"].values(), key=lambda t: t["W"])
+        hyb["all_device_speedup_over_best_hybrid"] = best["W"] / (r64["ms_per_step"] * 1e-3)
+        torch.cuda.empty_cache()
+
     out = {
         "metric": METRIC,
         "value": v64,
@@ -313,6 +410,8 @@ def main():
                             lu_only_ms=lu32_ms, refine_ms=ref_ms,
                             refine_sweeps_max=int(iters32.max()), refine_sweeps_mean=float(iters32.mean())),
         "adjoint": adj,
+        "genetic_algorithm": ga,
+        "hybrid_ablation": hyb,
         "roofline": roof,
         "roofline_kernels": kern,
         "other_workloads": side,
