@@ -69,6 +69,7 @@ def _args():
     ap.add_argument("--no-side", action="store_true", help="skip the uneven and large-panel batches")
     ap.add_argument("--no-ga", action="store_true", help="skip the on-device genetic-algorithm generation")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the host-LAPACK hybrid ablation")
+    ap.add_argument("--no-hs", action="store_true", help="skip the Hess-Smith step on the same batch")
     ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of a graph replay")
     ap.add_argument("--wave-limit", type=int, default=None,
                     help="largest system order for the one-wavefront LU (0 = workgroup LU only); "
@@ -297,7 +298,7 @@ def main():
             torch.cuda.empty_cache()
 
     # the Hess-Smith formulation on the same batch and nodes
-    if not a.no_side and a.batch is None:
+    if not a.no_hs and a.batch is None:
         hs = {}
         for tag, prec in (("fp64", P.PANEL_FP64), ("fp32_refine", P.PANEL_FP32_REFINE)):
             sh = P.PanelSolver(noff, aoff, prec, formulation=P.PANEL_HESS_SMITH)

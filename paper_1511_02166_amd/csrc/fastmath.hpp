@@ -14,7 +14,9 @@
 // R(z) = z (2/3 + 2z/5 + 2z^2/7 + ...), |s| <= 0.172.  Since 2s = f - s f,
 // log(m) = f - s (f - R): the leading term f is exact and the rounding of the
 // small correction barely matters.  e ln2 is added in two pieces, the high
-// one with few enough bits that e * LN2_HI is exact.
+// one with few enough bits that e * LN2_HI is exact (Cody and Waite's
+// argument-reduction split; the constants are ln 2 and pi themselves, cut
+// into a short head and the remainder).
 //
 // atan2(y, x): fold to t = min(|x|,|y|) / max(|x|,|y|) in [0, 1], pick the
 // nearest centre c = i/4 (i = 0..4), and use atan(t) = atan(c) + atan(u) with
