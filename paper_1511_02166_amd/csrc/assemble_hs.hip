@@ -22,8 +22,9 @@
 // Assembly: a thread owns one row (control point) and walks all N panels, so
 // the logarithm of |m_j - P_{i+1}|^2 is shared with the next panel and both
 // row sums are formed in registers (no cross-workgroup reduction); lanes
-// write consecutive rows of a column.  A one-wavefront pass per airfoil then
-// forms the Kutta row from rows 0 and N-1 of T.
+// write consecutive rows of a column.  One more block per airfoil in the same
+// launch forms the Kutta row from the two trailing-edge control points
+// (reading rows 0 and N-1 of T back would be two strided passes).
 #include "fastmath.hpp"
 #include "panel_internal.hpp"
 #include "wave.hpp"
@@ -35,6 +36,59 @@ constexpr double kInv2Pi = 0.15915494309189535;   // 1 / (2 pi)
 constexpr double kPi = 3.141592653589793;
 constexpr int HS_TPB = 256;
 
+// Kutta row, formed by its own block of the assembly launch: for each panel
+// i (a thread per panel), M[N][i] = T[0][i] + T[N-1][i], the tangential
+// source entries of the two trailing-edge control points evaluated as the
+// row threads evaluate them; M[N][N] = sum_i (A[0][i] + A[N-1][i]) (the
+// vortex columns are the row sums of A); right-hand side
+// -V_inf . (t_0 + t_{N-1}).
+template <bool MIXED>
+__device__ void hs_kutta_row(const WsView &v, const AirfoilMeta &mt, const double *sx, const double *sy,
+                             const double *stx, const double *sty, const double *sca, const double *ssa,
+                             double vinf) {
+    const int N = mt.N, n1 = mt.n1, K = mt.K, ld = mt.ld;
+    double *A = v.a64 + mt.a_off;
+    float *A32 = MIXED ? v.a32 + mt.a_off : nullptr;
+    __shared__ double red[HS_TPB / 64];
+    double vort = 0.0;
+    for (int i = threadIdx.x; i < N; i += HS_TPB) {
+        double t2 = 0.0;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int j = side == 0 ? 0 : N - 1;
+            const double mx = 0.5 * (sx[j] + sx[j + 1]), my = 0.5 * (sy[j] + sy[j + 1]);
+            const double d1x = mx - sx[i], d1y = my - sy[i], d2x = mx - sx[i + 1], d2y = my - sy[i + 1];
+            double beta = patan2(-(d1x * d2y - d1y * d2x), d1x * d2x + d1y * d2y);
+            double lg = 0.5 * (plog(d1x * d1x + d1y * d1y) - plog(d2x * d2x + d2y * d2y));
+            if (i == j) {
+                beta = kPi;
+                lg = 0.0;
+            }
+            const double c = stx[i] * stx[j] + sty[i] * sty[j];
+            const double s = stx[i] * sty[j] - sty[i] * stx[j];
+            vort += kInv2Pi * (lg * s + beta * c);
+            t2 += kInv2Pi * (lg * c - beta * s);
+        }
+        A[(size_t)i * ld + N] = t2;
+        if (MIXED) A32[(size_t)i * ld + N] = (float)t2;
+    }
+    vort = wave_sum(vort);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = vort;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < HS_TPB / 64; ++w) sum += red[w];
+        A[(size_t)N * ld + N] = sum;
+        if (MIXED) A32[(size_t)N * ld + N] = (float)sum;
+    }
+    const double tx = stx[0] + stx[N - 1], ty = sty[0] + sty[N - 1];
+    for (int k = threadIdx.x; k < K; k += HS_TPB) {
+        const double r = -vinf * (sca[k] * tx + ssa[k] * ty);
+        A[(size_t)(n1 + k) * ld + N] = r;
+        if (MIXED) A32[(size_t)(n1 + k) * ld + N] = (float)r;
+    }
+}
+
 template <bool MIXED>
 __global__ __launch_bounds__(HS_TPB) void assemble_hs_kernel(WsView v, const double *__restrict__ xy,
                                                              const double *__restrict__ alpha_in,
@@ -42,8 +96,9 @@ __global__ __launch_bounds__(HS_TPB) void assemble_hs_kernel(WsView v, const dou
     const int b = blockIdx.x;
     const AirfoilMeta mt = v.meta[b];
     const int N = mt.N, n1 = mt.n1, K = mt.K, ld = mt.ld;
+    const bool kutta = blockIdx.y == gridDim.y - 1;   // the last y-block forms the Kutta row
     const int r0 = blockIdx.y * HS_TPB;
-    if (r0 >= ld) return;
+    if (!kutta && r0 >= ld) return;
 
     __shared__ double sx[PANEL_NMAX + 1], sy[PANEL_NMAX + 1];
     __shared__ double stx[PANEL_NMAX], sty[PANEL_NMAX];
@@ -80,6 +135,11 @@ __global__ __launch_bounds__(HS_TPB) void assemble_hs_kernel(WsView v, const dou
         }
     }
     if (bad) atomicOr(&sbad, 1);
+    if (kutta) {
+        __syncthreads();
+        hs_kutta_row<MIXED>(v, mt, sx, sy, stx, sty, sca, ssa, vinf);
+        return;
+    }
     if (blockIdx.y == 0) {
         if (threadIdx.x < K) v.alpha[mt.alpha_off + threadIdx.x] = alpha_in[mt.alpha_off + threadIdx.x];
         if (threadIdx.x == 0) {
@@ -96,7 +156,7 @@ __global__ __launch_bounds__(HS_TPB) void assemble_hs_kernel(WsView v, const dou
     const int j = r0 + threadIdx.x;
     if (j >= ld) return;
     if (j >= N) {
-        // row N (the Kutta row) comes from the second pass; rows past it are
+        // row N (the Kutta row) comes from the Kutta block; rows past it are
         // zero padding of every column
         if (j > N) {
             for (int c = 0; c < n1 + K; ++c) {
@@ -143,30 +203,6 @@ __global__ __launch_bounds__(HS_TPB) void assemble_hs_kernel(WsView v, const dou
         const double r = -vinf * (sca[k] * tjy - ssa[k] * tjx);   // -V_inf . n_j
         A[(size_t)(n1 + k) * ld + j] = r;
         if (MIXED) A32[(size_t)(n1 + k) * ld + j] = (float)r;
-    }
-}
-
-// Kutta row: M[N][i] = T[0][i] + T[N-1][i], right-hand side
-// -V_inf . (t_0 + t_{N-1}); one wavefront per airfoil.
-template <bool MIXED>
-__global__ __launch_bounds__(64) void hs_kutta_kernel(WsView v, double vinf) {
-    const int b = blockIdx.x;
-    const AirfoilMeta mt = v.meta[b];
-    const int N = mt.N, n1 = mt.n1, K = mt.K, ld = mt.ld;
-    double *A = v.a64 + mt.a_off;
-    float *A32 = MIXED ? v.a32 + mt.a_off : nullptr;
-    const double *T = v.tg + mt.a_off;
-    for (int i = threadIdx.x; i < n1; i += 64) {
-        const double r = T[(size_t)i * ld] + T[(size_t)i * ld + N - 1];
-        A[(size_t)i * ld + N] = r;
-        if (MIXED) A32[(size_t)i * ld + N] = (float)r;
-    }
-    const PanelGeom g0 = v.geom[mt.panel_off], ge = v.geom[mt.panel_off + N - 1];
-    for (int k = threadIdx.x; k < K; k += 64) {
-        const double a = v.alpha[mt.alpha_off + k];
-        const double r = -vinf * (cos(a) * (g0.tx + ge.tx) + sin(a) * (g0.ty + ge.ty));
-        A[(size_t)(n1 + k) * ld + N] = r;
-        if (MIXED) A32[(size_t)(n1 + k) * ld + N] = (float)r;
     }
 }
 
@@ -249,14 +285,12 @@ __global__ __launch_bounds__(HS_TPB) void forces_hs_kernel(WsView v, double *__r
 
 hipError_t launch_assemble_hs(const WsView &v, int32_t B, int32_t max_ld, int32_t mixed, const double *xy,
                               const double *alpha, const double *chord, double vinf, hipStream_t stream) {
-    dim3 grid(B, (max_ld + HS_TPB - 1) / HS_TPB);
-    if (mixed) {
+    // row blocks, then one block per airfoil for the Kutta row
+    dim3 grid(B, (max_ld + HS_TPB - 1) / HS_TPB + 1);
+    if (mixed)
         assemble_hs_kernel<true><<<grid, HS_TPB, 0, stream>>>(v, xy, alpha, chord, vinf);
-        hs_kutta_kernel<true><<<B, 64, 0, stream>>>(v, vinf);
-    } else {
+    else
         assemble_hs_kernel<false><<<grid, HS_TPB, 0, stream>>>(v, xy, alpha, chord, vinf);
-        hs_kutta_kernel<false><<<B, 64, 0, stream>>>(v, vinf);
-    }
     return hipGetLastError();
 }
 
