@@ -113,7 +113,7 @@ __device__ __forceinline__ V block_dot(const T *p, int ld, const V *yb, V s) {
 
 // Back substitution U x = y (U upper, column-major in global memory), y in LDS.
 template <typename T, typename V, int TB = TPB>
-__device__ void trsv_upper(const T *U, int ld, int n, V *y, T *sblk) {
+__device__ __forceinline__ void trsv_upper(const T *U, int ld, int n, V *y, T *sblk) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = (n + SB - 1) / SB;
     for (int blk = nblk - 1; blk >= 0; --blk) {
@@ -150,7 +150,7 @@ __device__ void trsv_upper(const T *U, int ld, int n, V *y, T *sblk) {
 
 // Forward substitution L y = b (unit lower), y in LDS.
 template <typename T, typename V, int TB = TPB>
-__device__ void trsv_lower_unit(const T *L, int ld, int n, V *y, T *sblk) {
+__device__ __forceinline__ void trsv_lower_unit(const T *L, int ld, int n, V *y, T *sblk) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = (n + SB - 1) / SB;
     for (int blk = 0; blk < nblk; ++blk) {
@@ -172,6 +172,132 @@ __device__ void trsv_lower_unit(const T *L, int ld, int n, V *y, T *sblk) {
         for (int r = rb + w + tid; r < n; r += TB) {
             // rows below a block exist only when the block is full (w == SB)
             y[r] = block_dot<T, V>(L + (size_t)rb * ld + r, ld, y + rb, y[r]);
+        }
+        __syncthreads();
+    }
+}
+
+// ---- triangular solves on NR vectors at once (the refinement) -----------------
+// As above, but every 64x64 diagonal block and every row of the matrix is
+// read once for all NR right-hand sides: y[r] (r < NR) are LDS vectors of
+// stride ys.  The serial chain of a diagonal block (64 broadcast steps) is
+// shared by the NR vectors.
+template <int NR>
+__device__ __forceinline__ void block_dot_n(const float *p, int ld, const float *yb, int ys, float (&s)[NR]) {
+    // one running address (a column step per load): precomputed addresses
+    // for all 64 columns would hold 128 registers
+    const size_t step = (size_t)opaque_s(ld);
+#pragma unroll 1
+    for (int j0 = 0; j0 < SB; j0 += 16) {
+        float a[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            a[jj] = *p;
+            p += step;
+            asm volatile("" : "+v"(p));   // keep the walk sequential (no table of offsets)
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) s[r] -= a[jj] * yb[r * ys + j0 + jj];
+            if ((jj & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+template <int NR, int TB>
+__device__ __forceinline__ void trsm_lower_unit(const float *L, int ld, int n, int nr, float *y, int ys, float *sblk) {
+    ld = opaque_s(ld);   // address arithmetic formed here, not hoisted to the kernel entry
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nblk = (n + SB - 1) / SB;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int rb = blk * SB, w = min(SB, n - rb);
+        for (int idx = tid; idx < SB * SB; idx += TB) {
+            const int c = idx >> 6, r = idx & 63;
+            sblk[idx] = (c < w && r < w && r > c) ? L[(size_t)(rb + c) * ld + rb + r] : 0.0f;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            float yi[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) yi[r] = (r < nr && lane < w) ? y[r * ys + rb + lane] : 0.0f;
+#pragma unroll 2
+            for (int j = 0; j < w; ++j) {
+                const float lj = sblk[j * SB + lane];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const float xj = readlane_t(yi[r], j);
+                    if (lane > j) yi[r] -= lj * xj;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (r < nr && lane < w) y[r * ys + rb + lane] = yi[r];
+        }
+        __syncthreads();
+        for (int row = rb + w + tid; row < n; row += TB) {
+            float acc[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[r] = y[r * ys + row];
+            block_dot_n<NR>(L + (size_t)rb * ld + row, ld, y + rb, ys, acc);
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (r < nr) y[r * ys + row] = acc[r];
+        }
+        __syncthreads();
+    }
+}
+
+template <int NR, int TB>
+__device__ __forceinline__ void trsm_upper(const float *U, int ld, int n, int nr, float *y, int ys, float *sblk) {
+    ld = opaque_s(ld);   // address arithmetic formed here, not hoisted to the kernel entry
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nblk = (n + SB - 1) / SB;
+    for (int blk = nblk - 1; blk >= 0; --blk) {
+        const int rb = blk * SB, w = min(SB, n - rb);
+        for (int idx = tid; idx < SB * SB; idx += TB) {
+            const int c = idx >> 6, r = idx & 63;
+            sblk[idx] = (c < w && r <= c) ? U[(size_t)(rb + c) * ld + rb + r] : 0.0f;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            float yi[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) yi[r] = (r < nr && lane < w) ? y[r * ys + rb + lane] : 0.0f;
+            const float dinv = (lane < w) ? 1.0f / sblk[lane * SB + lane] : 0.0f;
+#pragma unroll 2
+            for (int j = w - 1; j >= 0; --j) {
+                const float uj = sblk[j * SB + lane];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    if (lane == j) yi[r] *= dinv;
+                    const float xj = readlane_t(yi[r], j);
+                    if (lane < j) yi[r] -= uj * xj;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (r < nr && lane < w) y[r * ys + rb + lane] = yi[r];
+        }
+        __syncthreads();
+        for (int row = tid; row < rb; row += TB) {
+            const float *up = U + (size_t)rb * ld + row;
+            float acc[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[r] = y[r * ys + row];
+            if (w == SB) {   // every block but the last, partial one
+                block_dot_n<NR>(up, ld, y + rb, ys, acc);
+            } else {
+                for (int j = 0; j < w; ++j) {
+                    const float a = up[(size_t)j * ld];
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) acc[r] -= a * y[r * ys + rb + j];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (r < nr) y[r * ys + row] = acc[r];
         }
         __syncthreads();
     }
@@ -601,18 +727,23 @@ __global__ __launch_bounds__(TB, (TB <= 256 && RMAX <= 3) ? 2 : 1) void lu_kerne
 // serving KG right-hand sides); for each right-hand side not yet converged:
 // stop if r is at the FP64 backward-error floor, ||r||_inf <= sqrt(n) eps
 // ||A||_inf ||x||_inf (no further sweep can improve x); otherwise
-// d = U^{-1} L^{-1} P r in FP32, x += d, and stop once ||d||_inf <= tol
-// ||x||_inf.
-constexpr int KG = 2;   // right-hand sides refined per pass over A
+// d = U^{-1} L^{-1} P r in FP32 (one pass over the factors for the group),
+// x += d, and stop by the rule of refined_enough.  KG = 4: eight would spill
+// registers in the residual pass of a 512-thread workgroup.
+constexpr int KG = 4;
+constexpr int YS = PANEL_NMAX + 1;
 template <int TB> struct WgRefLds {
-    double sx[KG][PANEL_NMAX + 1];
-    double sr[KG][PANEL_NMAX + 1];
-    float sd[PANEL_NMAX + 1];
-    int perm[PANEL_NMAX + 1];
-    double red[3][TB / 64];
+    double sx[KG][YS];   // current solutions
+    float sd[KG][YS];    // residuals in pivot order, then the corrections
+    int perm[YS];        // position i of the factored system holds row perm[i]
+    int pinv[YS];        // and row r sits at position pinv[r]
+    double red[3][KG][TB / 64];
     float sblk[SB * SB];
 };
 
+// FP64 refinement of the FP32 solutions of one airfoil, KG right-hand sides
+// per pass: one read of A64 forms their residuals, one read of the FP32
+// factors their corrections.
 template <int TB>
 __device__ __forceinline__ void wg_refine(const WsView &v, int b, int32_t *__restrict__ info, double tol,
                                           int max_iter, WgRefLds<TB> &S) {
@@ -630,42 +761,36 @@ __device__ __forceinline__ void wg_refine(const WsView &v, int b, int32_t *__res
     const float *LU = v.a32 + mt.a_off;
     const int32_t *piv = v.piv + mt.piv_off;
     double *X = v.x + mt.x_off;
-    double (*sx)[PANEL_NMAX + 1] = S.sx;
-    double (*sr)[PANEL_NMAX + 1] = S.sr;
-    float *sd = S.sd;
-    int *perm = S.perm;
-    double (*red)[TB / 64] = S.red;
-    float *sblk = S.sblk;
     if (tid == 0) {
-        for (int i = 0; i < n; ++i) perm[i] = i;
+        for (int i = 0; i < n; ++i) S.perm[i] = i;
         for (int i = 0; i < n; ++i) {
             const int p = piv[i];
-            const int t0 = perm[i];
-            perm[i] = perm[p];
-            perm[p] = t0;
+            const int t0 = S.perm[i];
+            S.perm[i] = S.perm[p];
+            S.perm[p] = t0;
         }
     }
-    // block-wide max of three values (all threads receive the result)
-    auto bmax3 = [&](double &a0, double &a1, double &a2) {
-        for (int off = 32; off > 0; off >>= 1) {
-            a0 = fmax(a0, __shfl_xor(a0, off));
-            a1 = fmax(a1, __shfl_xor(a1, off));
-            a2 = fmax(a2, __shfl_xor(a2, off));
-        }
-        if (lane == 0) {
-            red[0][wave] = a0;
-            red[1][wave] = a1;
-            red[2][wave] = a2;
-        }
+    __syncthreads();
+    for (int i = tid; i < n; i += TB) S.pinv[S.perm[i]] = i;
+    // block-wide maxima of three values per right-hand side
+    auto bmax = [&](double (&a)[3][KG]) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int r = 0; r < KG; ++r) {
+                double x = a[q][r];
+                for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
+                if (lane == 0) S.red[q][r][wave] = x;
+            }
         __syncthreads();
-        a0 = red[0][0];
-        a1 = red[1][0];
-        a2 = red[2][0];
-        for (int w = 1; w < TB / 64; ++w) {
-            a0 = fmax(a0, red[0][w]);
-            a1 = fmax(a1, red[1][w]);
-            a2 = fmax(a2, red[2][w]);
-        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int r = 0; r < KG; ++r) {
+                double x = S.red[q][r][0];
+                for (int w = 1; w < TB / 64; ++w) x = fmax(x, S.red[q][r][w]);
+                a[q][r] = x;
+            }
         __syncthreads();
     };
     const double floor_c = sqrt((double)n) * 2.220446049250313e-16;
@@ -675,7 +800,7 @@ __device__ __forceinline__ void wg_refine(const WsView &v, int b, int32_t *__res
     for (int k0 = 0; k0 < mt.K; k0 += KG) {
         const int kn = min(KG, mt.K - k0);
         for (int kk = 0; kk < kn; ++kk)
-            for (int i = tid; i < n; i += TB) sx[kk][i] = X[(size_t)(k0 + kk) * n + i];
+            for (int i = tid; i < n; i += TB) S.sx[kk][i] = X[(size_t)(k0 + kk) * n + i];
         __syncthreads();
         bool conv[KG];
         int sweeps[KG];
@@ -691,68 +816,87 @@ __device__ __forceinline__ void wg_refine(const WsView &v, int b, int32_t *__res
 #pragma unroll
             for (int kk = 0; kk < KG; ++kk) all = all && conv[kk];
             if (all) break;
+            // r = b - A x for the group, one pass over A; the residual goes
+            // straight to its pivot position (FP32) and its size is kept
+            double m[3][KG];
+#pragma unroll
+            for (int kk = 0; kk < KG; ++kk) m[0][kk] = m[1][kk] = m[2][kk] = 0.0;
             double rowmax = 0.0;
+            const bool first_pass = anrm < 0.0;
+            const int ldr = opaque_s(ld);
             for (int i = tid; i < n; i += TB) {
-                double s0 = A[(size_t)(n + k0) * ld + i];
-                double s1 = (kn > 1) ? A[(size_t)(n + k0 + 1) * ld + i] : 0.0;
+                double sk[KG];
+#pragma unroll
+                for (int kk = 0; kk < KG; ++kk) sk[kk] = (kk < kn) ? A[(size_t)(n + k0 + kk) * ldr + i] : 0.0;
                 double ra = 0.0;
-                const bool first_pass = anrm < 0.0;
                 // JR columns per round trip: all their loads are issued
                 // before the first product (left to itself the compiler put
                 // a wait after every load, one memory latency per element)
                 for (int j0 = 0; j0 < n; j0 += JR) {
                     double a[JR];
 #pragma unroll
-                    for (int jj = 0; jj < JR; ++jj) a[jj] = A[(size_t)min(j0 + jj, n - 1) * ld + i];
+                    for (int jj = 0; jj < JR; ++jj) a[jj] = A[(size_t)min(j0 + jj, n - 1) * ldr + i];
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int jj = 0; jj < JR; ++jj) {
                         if (j0 + jj < n) {
-                            s0 -= a[jj] * sx[0][j0 + jj];
-                            if (kn > 1) s1 -= a[jj] * sx[1][j0 + jj];
+#pragma unroll
+                            for (int kk = 0; kk < KG; ++kk)
+                                if (kk < kn) sk[kk] -= a[jj] * S.sx[kk][j0 + jj];
                             if (first_pass) ra += fabs(a[jj]);
                         }
+                        // keep the broadcast reads of x from being hoisted all at once
+                        if ((jj & 3) == 3) __builtin_amdgcn_sched_barrier(0);
                     }
                 }
-                sr[0][i] = s0;
-                sr[1][i] = s1;
+                const int pi = S.pinv[i];
+#pragma unroll
+                for (int kk = 0; kk < KG; ++kk) {
+                    if (kk < kn) {
+                        S.sd[kk][pi] = (float)sk[kk];
+                        m[0][kk] = fmax(m[0][kk], fabs(sk[kk]));
+                        m[1][kk] = fmax(m[1][kk], fabs(S.sx[kk][i]));
+                    }
+                }
                 rowmax = fmax(rowmax, ra);
             }
-            if (anrm < 0.0) {
-                double u0 = 0.0, u1 = 0.0;
-                bmax3(rowmax, u0, u1);
-                anrm = rowmax;
-            }
-            __syncthreads();
+            m[2][0] = rowmax;
+            bmax(m);
+            if (anrm < 0.0) anrm = m[2][0];
+            // a right-hand side whose residual is at the FP64 backward-error
+            // floor is done; the others take a correction
+            bool need = false;
 #pragma unroll
             for (int kk = 0; kk < KG; ++kk) {
-                if (conv[kk]) continue;
-                double rmax = 0.0, xmax = 0.0, unused = 0.0;
-                for (int i = tid; i < n; i += TB) {
-                    rmax = fmax(rmax, fabs(sr[kk][i]));
-                    xmax = fmax(xmax, fabs(sx[kk][i]));
+                if (!conv[kk] && m[0][kk] <= floor_c * anrm * m[1][kk]) conv[kk] = true;
+                if (!conv[kk]) need = true;
+            }
+            if (!need) break;
+            trsm_lower_unit<KG, TB>(LU, ld, n, kn, &S.sd[0][0], YS, S.sblk);
+            trsm_upper<KG, TB>(LU, ld, n, kn, &S.sd[0][0], YS, S.sblk);
+            double d[3][KG];
+#pragma unroll
+            for (int kk = 0; kk < KG; ++kk) d[0][kk] = d[1][kk] = d[2][kk] = 0.0;
+            for (int i = tid; i < n; i += TB) {
+#pragma unroll
+                for (int kk = 0; kk < KG; ++kk) {
+                    if (kk < kn && !conv[kk]) {
+                        const double dd = (double)S.sd[kk][i];
+                        const double x1 = S.sx[kk][i] + dd;
+                        S.sx[kk][i] = x1;
+                        d[0][kk] = fmax(d[0][kk], fabs(dd));
+                        d[1][kk] = fmax(d[1][kk], fabs(x1));
+                    }
                 }
-                bmax3(rmax, xmax, unused);
-                if (rmax <= floor_c * anrm * xmax) {
-                    conv[kk] = true;
-                    continue;
+            }
+            bmax(d);
+#pragma unroll
+            for (int kk = 0; kk < KG; ++kk) {
+                if (kk < kn && !conv[kk]) {
+                    ++sweeps[kk];
+                    conv[kk] = wv::refined_enough(d[0][kk], dprev[kk], d[1][kk], tol);
+                    dprev[kk] = d[0][kk];
                 }
-                for (int i = tid; i < n; i += TB) sd[i] = (float)sr[kk][perm[i]];
-                __syncthreads();
-                trsv_lower_unit<float, float, TB>(LU, ld, n, sd, sblk);
-                trsv_upper<float, float, TB>(LU, ld, n, sd, sblk);
-                double dmax = 0.0, xn = 0.0;
-                for (int i = tid; i < n; i += TB) {
-                    const double d = (double)sd[i];
-                    const double x1 = sx[kk][i] + d;
-                    sx[kk][i] = x1;
-                    dmax = fmax(dmax, fabs(d));
-                    xn = fmax(xn, fabs(x1));
-                }
-                bmax3(dmax, xn, unused);
-                ++sweeps[kk];
-                conv[kk] = wv::refined_enough(dmax, dprev[kk], xn, tol);
-                dprev[kk] = dmax;
             }
         }
 #pragma unroll
@@ -761,7 +905,7 @@ __device__ __forceinline__ void wg_refine(const WsView &v, int b, int32_t *__res
             worst = max(worst, sweeps[kk]);
         }
         for (int kk = 0; kk < kn; ++kk)
-            for (int i = tid; i < n; i += TB) X[(size_t)(k0 + kk) * n + i] = sx[kk][i];
+            for (int i = tid; i < n; i += TB) X[(size_t)(k0 + kk) * n + i] = S.sx[kk][i];
         __syncthreads();
     }
     if (tid == 0) {
