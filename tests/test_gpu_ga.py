@@ -159,13 +159,14 @@ def _optimizer(pop=64, N=128, alpha=(0.0, 4 * DEG), seed=5, **kw):
                               seed=seed, **kw), prob
 
 
-def test_ga_generation_matches_the_oracle_chain():
+@pytest.mark.parametrize("formulation,precision", [(0, 0), (1, 0), (0, 1)], ids=["stream-fp64", "hs-fp64", "stream-fp32"])
+def test_ga_generation_matches_the_oracle_chain(formulation, precision):
     # contours -> solve -> viscous correction -> fitness on the GPU against
     # the oracle's chain on the same genomes; then the same uniforms breed
     # the same next generation
     import torch
-    _say("GA generation vs oracle chain")
-    opt, prob = _optimizer(re=1e6)
+    _say(f"GA generation vs oracle chain, formulation {formulation}, precision {precision}")
+    opt, prob = _optimizer(re=1e6, formulation=formulation, precision=precision)
     opt.initialize(_dev(synth.ga_uniforms(6, opt.pop * prob.G)))
     fit = opt.evaluate().cpu().numpy()
     genome = opt.genome.cpu().numpy()
@@ -175,7 +176,7 @@ def test_ga_generation_matches_the_oracle_chain():
     noff = (np.arange(opt.pop + 1) * (opt.N + 1)).astype(np.int32)
     aoff = (np.arange(opt.pop + 1) * K).astype(np.int32)
     xy = nodes.reshape(-1)
-    ref = oracle.solve_batch(xy, noff, alpha, aoff)
+    ref = oracle.solve_batch(xy, noff, alpha, aoff, formulation=("stream", "hess_smith")[formulation])
     ld = np.concatenate([oracle.thwaites(nodes[b], alpha[K * b:K * b + K], ref["gamma"][b * K * opt.N:(b + 1) * K * opt.N],
                                          ref["cl"][K * b:K * b + K], 1e6)["ld"] for b in range(opt.pop)])
     rfit = oracle.ga_fitness(aoff, ld, ref["info"])
@@ -183,7 +184,7 @@ def test_ga_generation_matches_the_oracle_chain():
     assert np.array_equal(ok, np.isfinite(fit))
     e = np.max(np.abs(fit[ok] - rfit[ok]) / np.abs(rfit[ok]))
     _say(f"  fitness {np.min(rfit[ok]):.1f}..{np.max(rfit[ok]):.1f} (usable {ok.mean():.2f}), rel err {e:.1e}")
-    assert e < 1e-9
+    assert e < (1e-9 if precision == 0 else 1e-7)
     assert np.array_equal(np.argsort(fit, kind="stable"), np.argsort(rfit, kind="stable"))
     u = synth.ga_uniforms(7, opt.u_gen.numel())[0]
     opt.record()
