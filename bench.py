@@ -50,7 +50,7 @@ ASM_FLOPS_PER_ENTRY = 118.0
 # on, which is identified by the SHA-256 prefix of that source file.
 LU_TRAFFIC = {("lu_wave_impl.hpp", "efb29edbf3f9df7f"): 10_221_091_922}   # one wavefront per airfoil
 
-# Host threads for the oracle: the box assigns 16 host cores to each GPU.
+# Host threads for the oracle: at most 16, the host cores a benchmark node gives each GPU.
 CPU_SHARE = 16
 
 
