@@ -135,6 +135,7 @@ template <typename T> struct WaveLds {
     int mv_dst[2 * WNB];     //   ends at position mv_dst[m]
     int nmv;
     int ipiv[WNB];           // LAPACK pivots of the last panel (positions)
+    T ub[WSP - WNB][WNB];    // U rows of the next panel's columns (left-looking step)
 };
 
 // ---- block update after pivot panels: band solve + trailing product --------
@@ -155,7 +156,7 @@ template <typename T> struct WaveLds {
 // of the band past n are zero padding (linv is the identity there).
 // One chunk of NT 16-column tiles starting at column cs (columns past c1
 // are clamped for the loads and never stored).
-template <typename T, int NBLK, int NT>
+template <typename T, int NBLK, int NT, bool TRAIL = true>
 __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int kend, int cs, int c1,
                                              const WaveLds<T> &S, int slot0, int nblk) {
     ld = opaque_s(ld);
@@ -219,7 +220,7 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
                 if (s < 4 * nblk) up[4 * s] = uf[t][s];
         }
     }
-    if (kend >= n) return;
+    if (!TRAIL || kend >= n) return;
 
     // trailing product A[kend:n, cs:cs+16NT) -= A[kend:n, band] U
     int coff[NT][4];   // element offsets of this lane's C columns (clamped)
@@ -420,7 +421,8 @@ __device__ __forceinline__ void wave_cols(T (&p)[R][WNB], int (&pos)[R], unsigne
 
 // ---- factor the panel of columns k0..k0+nb-1 (rows k0..n-1, R = rows/64) --
 template <typename T, int R>
-__device__ __forceinline__ void wave_panel(T *A, int ld, int n, int k0, int nb, int32_t *piv, int &info, WaveLds<T> &S) {
+__device__ __forceinline__ void wave_panel(T *A, int ld, int n, int k0, int nb, int kb, int32_t *piv, int &info,
+                                           WaveLds<T> &S) {
     ld = opaque_s(ld);
     const int lane = wlane();
     T p[R][WNB];
@@ -436,6 +438,34 @@ __device__ __forceinline__ void wave_panel(T *A, int ld, int n, int k0, int nb, 
         for (int cc = 0; cc < WNB; ++cc) p[q][cc] = A[(size_t)(k0 + min(cc, nb - 1)) * ld + rr];
     }
     __builtin_amdgcn_sched_barrier(0);
+    // left-looking update from the super-panel's panels before this one
+    // (band rows kb..k0, U block in LDS): A[k0:n, panel] -= L[k0:n, kb:k0] U,
+    // on the vector ALUs in the row-per-lane layout of the factorisation, so
+    // the updated panel never goes back to memory before it is factored
+    // (the FP64 vector rate equals the FP64 matrix rate on this GPU)
+    // (up to four slots of rows: with five the registers would spill, and
+    // the caller updates such panels in memory first)
+    constexpr int JG = 2;   // band columns per round trip of L loads
+    if constexpr (R <= 4)
+    for (int j0 = kb; j0 < k0; j0 += JG) {
+        T l[JG][R];
+#pragma unroll
+        for (int jj = 0; jj < JG; ++jj)
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                l[jj][q] = A[(size_t)(j0 + jj) * ld + min(k0 + lane + WL * q, n - 1)];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int jj = 0; jj < JG; ++jj) {
+#pragma unroll
+            for (int cc = 0; cc < WNB; ++cc) {
+                const T u = S.ub[j0 + jj - kb][cc];
+#pragma unroll
+                for (int q = 0; q < R; ++q) p[q][cc] -= l[jj][q] * u;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int r = k0 + lane + WL * q;
@@ -589,11 +619,25 @@ __device__ __forceinline__ void wave_trsv_upper(const T *U, int ld, int n, T *y)
 }
 
 template <typename T, int R>
-__device__ __forceinline__ bool panel_if(int rows, T *A, int ld, int n, int k0, int nb, int32_t *piv,
+__device__ __forceinline__ bool panel_if(int rows, T *A, int ld, int n, int k0, int nb, int kb, int32_t *piv,
                                          int &info, WaveLds<T> &S) {
     if (rows != R) return false;
-    wave_panel<T, R>(A, ld, n, k0, nb, piv, info, S);
+    wave_panel<T, R>(A, ld, n, k0, nb, kb, piv, info, S);
     return true;
+}
+
+// U rows of the panel's columns [k0, k0 + nb) from the band kb..k0 (the
+// super-panel's panels before it), and the U block to LDS for the panel's
+// left-looking update.
+template <typename T, int NBLK>
+__device__ __forceinline__ void wave_band_u(T *A, int ld, int n, int kb, int k0, int nb, WaveLds<T> &S) {
+    update_chunk<T, NBLK, 1, false>(A, ld, n, kb, k0, k0, k0 + nb, S, 0, NBLK);
+    wave_sync();
+    ld = opaque_s(ld);
+    for (int idx = wlane(); idx < WNB * WNB * NBLK; idx += WL) {
+        const int j = idx / WNB, c = idx % WNB;
+        S.ub[j][c] = c < nb ? A[(size_t)(k0 + c) * ld + kb + j] : T(0);
+    }
 }
 
 // LDS of one wavefront's factorisation.
@@ -636,18 +680,27 @@ __device__ __forceinline__ void wave_lu(const WsView &v, int b, int32_t *__restr
         for (int k0 = K0; k0 < kend; k0 += WNB) {
             const int nb = min(WNB, n - k0);
             const int rows = (n - k0 + WL - 1) / WL;
-            // the panel's columns take the update from the super-panel's
-            // panels before it, all at once (left-looking inside the
-            // super-panel: each column block is read and written once)
-            if (k0 - K0 == WNB) wave_update<T, 1>(A, ld, n, K0, k0, k0, k0 + nb, S, 0);
-            if (k0 - K0 == 2 * WNB) wave_update<T, 2>(A, ld, n, K0, k0, k0, k0 + nb, S, 0);
-            if (k0 - K0 == 3 * WNB) wave_update<T, 3>(A, ld, n, K0, k0, k0, k0 + nb, S, 0);
+            // The panel's columns take the update from the super-panel's
+            // panels before it (left-looking inside the super-panel): their
+            // U rows here, the rows below inside the panel factorisation
+            // (in registers), or, for panels of five row slots, in memory.
+            int kb = K0;
+            if (rows <= 4) {
+                if (k0 - K0 == WNB) wave_band_u<T, 1>(A, ld, n, K0, k0, nb, S);
+                if (k0 - K0 == 2 * WNB) wave_band_u<T, 2>(A, ld, n, K0, k0, nb, S);
+                if (k0 - K0 == 3 * WNB) wave_band_u<T, 3>(A, ld, n, K0, k0, nb, S);
+            } else {
+                if (k0 - K0 == WNB) wave_update<T, 1>(A, ld, n, K0, k0, k0, k0 + nb, S, 0);
+                if (k0 - K0 == 2 * WNB) wave_update<T, 2>(A, ld, n, K0, k0, k0, k0 + nb, S, 0);
+                if (k0 - K0 == 3 * WNB) wave_update<T, 3>(A, ld, n, K0, k0, k0, k0 + nb, S, 0);
+                kb = k0;
+            }
             if (k0 > K0) wave_sync();
-            panel_if<T, 1>(rows, A, ld, n, k0, nb, piv, info, S) ||
-                panel_if<T, 2>(rows, A, ld, n, k0, nb, piv, info, S) ||
-                panel_if<T, 3>(rows, A, ld, n, k0, nb, piv, info, S) ||
-                panel_if<T, 4>(rows, A, ld, n, k0, nb, piv, info, S) ||
-                panel_if<T, 5>(rows, A, ld, n, k0, nb, piv, info, S);
+            panel_if<T, 1>(rows, A, ld, n, k0, nb, kb, piv, info, S) ||
+                panel_if<T, 2>(rows, A, ld, n, k0, nb, kb, piv, info, S) ||
+                panel_if<T, 3>(rows, A, ld, n, k0, nb, kb, piv, info, S) ||
+                panel_if<T, 4>(rows, A, ld, n, k0, nb, kb, piv, info, S) ||
+                panel_if<T, 5>(rows, A, ld, n, k0, nb, kb, piv, info, S);
             wave_sync();
             wave_moves<T>(A, ld, ncols, k0, nb, S);
             wave_linv<T>(S, (k0 - K0) / WNB);
