@@ -44,6 +44,13 @@ PEAK = {"f64": 78.6e12, "f32": 157.3e12, "hbm": 8.0e12}
 # combination; 39 FMA x 2 + 40 other FP64 instructions in total.
 ASM_FLOPS_PER_ENTRY = 118.0
 
+# FP64 operations per (control point, panel) pair of the adjoint's pair
+# pass, counted from its compiled gfx950 loop as the difference between
+# builds with five and four control-point slots per lane: 52 FMA x 2 + 63
+# other FP64 instructions (the logarithm, the arctangent and the derivative
+# algebra of the panel integral).
+ADJ_FLOPS_PER_PAIR = 167.0
+
 # HBM bytes moved by one launch of the FP64 LU kernel on the 2048 x N=256
 # batch, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's
 # readings (x2.0 and x1.0).  Valid only for the kernel source it was taken
@@ -234,10 +241,16 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / a.steps
+        na = wa.n_panels.astype(np.float64)
+        adj_flop = float(np.sum(na * na * ADJ_FLOPS_PER_PAIR + 2.0 * (na + 1) ** 2))
         adj = {"workload": f"adjoint1024: {wa.B} NACA sections, N=256, alpha=6 deg, FP64 factors",
                "gradients_per_s": wa.B / (ms * 1e-3), "backward_ms": ms, "forward_ms": fwd["ms_per_step"],
                "fwd_plus_bwd_per_s": wa.B / ((ms + fwd["ms_per_step"]) * 1e-3),
-               "bad_info": int(np.sum(sa.adj_info.cpu().numpy() != 0))}
+               "bad_info": int(np.sum(sa.adj_info.cpu().numpy() != 0)),
+               "roofline": {"bound": "alu", "achieved": adj_flop / (ms * 1e-3) / 1e12, "peak": PEAK["f64"] / 1e12,
+                            "unit": "TFLOP/s", "frac": adj_flop / (ms * 1e-3) / PEAK["f64"],
+                            "work": f"{ADJ_FLOPS_PER_PAIR:.0f} FP64 flops per (control point, panel) pair "
+                                    "+ 2 n1^2 for the transposed solve, per airfoil"}}
         del sa
 
     # roofline of every hot kernel of the step
