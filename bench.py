@@ -307,6 +307,25 @@ def main():
                           "fp64_ms_per_step": q64["ms_per_step"], "fp64_solves_per_s": ns / (q64["ms_per_step"] * 1e-3),
                           "fp32_refine_ms_per_step": q32["ms_per_step"],
                           "fp32_refine_solves_per_s": ns / (q32["ms_per_step"] * 1e-3)}
+            if not a.no_cpu_baseline:
+                # the oracle beside it, on an evenly spaced sample of the batch
+                # (the GPU's own nodes), host threads as for cpu_baseline
+                import oracle
+                S = {"uneven4096": 512, "large256": 32}[name]
+                idx = np.linspace(0, ws_.B - 1, S).astype(int)
+                sub = ws_.subset(idx)
+                xh = xs.cpu().numpy()
+                no = ws_.node_offsets()
+                xo = np.concatenate([xh[2 * no[b]:2 * no[b + 1]] for b in idx])
+                nthr = max(1, min(len(os.sched_getaffinity(0)), CPU_SHARE))
+                times = []
+                for _ in range(3):
+                    t0 = time.perf_counter()
+                    r = oracle.solve_batch(xo, sub.node_offsets(), sub.alpha_flat(), sub.alpha_offsets(), nthreads=nthr)
+                    times.append(time.perf_counter() - t0)
+                dt = statistics.median(times)
+                side[name]["cpu_oracle"] = {"solves_per_s": int(r["cl"].size) / dt, "cores": int(r["threads"]),
+                                            "sample": f"{S} of the {ws_.B} airfoils, median of 3 runs, {dt:.2f} s each"}
             del t64, t32
             torch.cuda.empty_cache()
 
