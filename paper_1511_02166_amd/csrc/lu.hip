@@ -35,7 +35,10 @@ constexpr int TPB = 256;   // threads per workgroup by default (4 wavefronts)
 constexpr int CH = 256;    // trailing columns per U12 chunk
 constexpr int SB = 64;     // rows per diagonal block in the triangular solves
 constexpr int SP = 64;     // super-panel width (rank of the big trailing update)
-constexpr int CT = 64;     // columns per LDS chunk of the rank-SP update
+// columns per LDS chunk of the rank-SP update: each chunk re-reads the
+// super-panel's L block, so a workgroup that has its CU to itself (512
+// threads) stages twice as many
+template <int TB> struct CtOf { static constexpr int v = TB >= 512 ? 128 : 64; };
 constexpr int JR = 16;     // columns per round trip in the refinement residual
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
@@ -585,9 +588,10 @@ __device__ __forceinline__ void gemm_sub(T *A, int ld, int rowA, int rowEnd, int
 // whole register file of one.
 // LDS of one workgroup's factorisation.
 template <typename T, int NB, int RMAX, int TB> struct WgLuLds {
+    static constexpr int UB = NB * (CH + 4) > CtOf<TB>::v * (SP + 1) ? NB * (CH + 4) : CtOf<TB>::v * (SP + 1);
     PanelLds<T, NB, RMAX, TB> L;
     T s_L11[NB][NB + 1];
-    T s_U[NB][CH + 4];   // also holds the CT x (SP + 1) band of step 6
+    T s_U[UB];   // NB x (CH + 4) U rows, or the CT x (SP + 1) band of step 6
     T y[PANEL_NMAX + 1];
 };
 
@@ -610,7 +614,8 @@ __device__ __forceinline__ void wg_lu(const WsView &v, int b, int32_t *__restric
 
     PanelLds<T, NB, RMAX, TB> &L = S.L;
     T (*s_L11)[NB + 1] = S.s_L11;
-    T (*s_U)[CH + 4] = S.s_U;
+    T (*s_U)[CH + 4] = reinterpret_cast<T (*)[CH + 4]>(S.s_U);
+    constexpr int CT = CtOf<TB>::v;
     int info = 0;
 
     // Super-panels of SP columns; inside, NB-column pivot panels update the
