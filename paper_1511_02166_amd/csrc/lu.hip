@@ -36,9 +36,10 @@ constexpr int CH = 256;    // trailing columns per U12 chunk
 constexpr int SB = 64;     // rows per diagonal block in the triangular solves
 constexpr int SP = 64;     // super-panel width (rank of the big trailing update)
 // columns per LDS chunk of the rank-SP update: each chunk re-reads the
-// super-panel's L block, so a workgroup that has its CU to itself (512
-// threads) stages twice as many
-template <int TB> struct CtOf { static constexpr int v = TB >= 512 ? 128 : 64; };
+// super-panel's L block, so a chunk is as wide as the LDS allows (one
+// 512-thread workgroup per CU: 256 columns, 130 KB of FP64 U band; two
+// 256-thread workgroups per CU: 128 columns)
+template <int TB> struct CtOf { static constexpr int v = TB >= 512 ? 256 : 128; };
 constexpr int JR = 16;     // columns per round trip in the refinement residual
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
