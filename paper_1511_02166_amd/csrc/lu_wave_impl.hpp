@@ -63,7 +63,7 @@ constexpr int WSP = 64;   // super-panel width (rank of the trailing update)
 // trailing columns whose U fragments are held in registers at once (as many
 // as fit in the register budget without spilling)
 template <typename T> struct Wct;
-template <> struct Wct<double> { static constexpr int v = 32; };
+template <> struct Wct<double> { static constexpr int v = 48; };
 template <> struct Wct<float> { static constexpr int v = 64; };
 constexpr int WNB = 16;   // pivot panel width
 
@@ -222,7 +222,18 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
     }
     if (!TRAIL || kend >= n) return;
 
-    // trailing product A[kend:n, cs:cs+16NT) -= A[kend:n, band] U
+    // trailing product A[kend:n, cs:cs+16NT) -= A[kend:n, band] U, formed as
+    // A + L (-U): the U fragments are negated once here, so the streamed L
+    // fragments go to the matrix cores as loaded (a sign flip on a loaded
+    // value makes the compiler wait for the load where it flips it, which
+    // would stall each tile on the next tile's prefetch)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int s = 0; s < S4; ++s) {
+            uf[t][s] = -uf[t][s];
+            asm volatile("" : "+v"(uf[t][s]));   // keep the flip here, not at each use
+        }
     int coff[NT][4];   // element offsets of this lane's C columns (clamped)
     bool cok[NT][4];
 #pragma unroll
@@ -244,7 +255,7 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
         auto load_tile = [&](int slot, int rt) {
             const int rr = min(rt + i16, n - 1);
 #pragma unroll
-            for (int s = 0; s < S4; ++s) lf[slot][s] = -lcol[(size_t)(4 * s) * ld + rr];
+            for (int s = 0; s < S4; ++s) lf[slot][s] = lcol[(size_t)(4 * s) * ld + rr];
 #pragma unroll
             for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -274,41 +285,63 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
             }
         }
     } else {
-        // 16 x 16NT x 64 per tile: the next tile's C block goes into a second
-        // accumulator set at the start, each of its L fragments into the
-        // register the current product has just consumed
+        // 16 x 16NT x 64 per tile.  The products start from zero and the
+        // tile's C block is added after them: C of the next tile is loaded
+        // right after this tile's stores, each L fragment of the next tile
+        // into the register this tile's product has just consumed.  Every
+        // wait is then for loads issued about one tile earlier.
         T lf[S4];
-        acc_t acc[NT], nxt[NT];
+        T cb[NT][4];
         const int rc = min(kend + i16, n - 1);
 #pragma unroll
-        for (int s = 0; s < S4; ++s) lf[s] = -lcol[(size_t)(4 * s) * ld + rc];
+        for (int s = 0; s < S4; ++s) lf[s] = lcol[(size_t)(4 * s) * ld + rc];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[t][e] = A[coff[t][e] + rc];
+            for (int e = 0; e < 4; ++e) cb[t][e] = A[coff[t][e] + rc];
+        // the first tile's operands complete here, so that inside the loop
+        // only the loop's own issue order decides what each product waits for
+#pragma unroll
+        for (int s = 0; s < S4; ++s) asm volatile("" ::"v"(lf[s]));
         for (int rt = kend; rt < n; rt += 16) {
             const int r = rt + i16;
             const int rn = min(r + 16, n - 1);   // next tile's row (clamped)
+            acc_t acc[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) nxt[t][e] = A[coff[t][e] + rn];
+                for (int e = 0; e < 4; ++e) acc[t][e] = T(0);
 #pragma unroll
             for (int s = 0; s < S4; ++s) {
 #pragma unroll
                 for (int t = 0; t < NT; ++t) acc[t] = mfma_t(uf[t][s], lf[s], acc[t]);
-                lf[s] = -lcol[(size_t)(4 * s) * ld + rn];
+                lf[s] = lcol[(size_t)(4 * s) * ld + rn];
             }
             if (r < n) {
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        if (cok[t][e]) A[coff[t][e] + r] = acc[t][e];
+                        if (cok[t][e]) A[coff[t][e] + r] = cb[t][e] + acc[t][e];
             }
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = nxt[t];
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) cb[t][e] = A[coff[t][e] + rn];
         }
+    }
+}
+
+// The last chunk of a block update: exactly as many 16-column tiles as are
+// left (1 .. R), so it makes one pass over L like a full chunk.
+template <typename T, int NBLK, int R>
+__device__ __forceinline__ void update_rest(int tiles, T *A, int ld, int n, int kb, int kend, int cs, int c1,
+                                            const WaveLds<T> &S, int slot0, int nblk) {
+    if constexpr (R >= 1) {
+        if (tiles == R)
+            update_chunk<T, NBLK, R>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
+        else
+            update_rest<T, NBLK, R - 1>(tiles, A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
     }
 }
 
@@ -317,18 +350,19 @@ __device__ __forceinline__ void wave_update(T *A, int ld, int n, int kb, int ken
                                             const WaveLds<T> &S, int slot0) {
     constexpr int NTM = Wct<T>::v / 16;
     const int nblk = min(NBLK, (kend - kb + WNB - 1) / WNB);
-    // full chunks, then a narrower one for the remainder (a trailing block
-    // of n1 + K columns is rarely a multiple of the chunk width)
+    // full chunks, then one of the remaining width (a trailing block of
+    // n1 + K columns is rarely a multiple of the chunk width)
+    // (FP32: at most two tiles at a time in the rest, which keeps the kernel
+    // free of scratch spills)
+    constexpr int RM = sizeof(T) == 8 ? NTM - 1 : 2;
     int cs = c0;
     for (; c1 - cs > 16 * (NTM - 1); cs += 16 * NTM)
         update_chunk<T, NBLK, NTM>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
-    if constexpr (NTM > 2) {
-        if (c1 - cs > 16) {
-            update_chunk<T, NBLK, 2>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
-            cs += 32;
-        }
+    while (cs < c1) {
+        const int tiles = min(RM, (c1 - cs + 15) / 16);
+        update_rest<T, NBLK, RM>(tiles, A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
+        cs += 16 * tiles;
     }
-    if (cs < c1) update_chunk<T, NBLK, 1>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
 }
 
 // ---- one column step of the panel factorisation (C is compile-time) --------
