@@ -479,7 +479,9 @@ __device__ __forceinline__ void wave_panel(T *A, int ld, int n, int k0, int nb, 
     // (the FP64 vector rate equals the FP64 matrix rate on this GPU)
     // (up to four slots of rows: with five the registers would spill, and
     // the caller updates such panels in memory first)
-    constexpr int JG = 2;   // band columns per round trip of L loads
+    // band columns per round trip of L loads: as many as the registers left
+    // by the panel's R row slots allow (k0 - kb is a multiple of 16)
+    constexpr int JG = R == 1 ? 16 : R == 2 ? 8 : R == 3 ? 4 : 2;
     if constexpr (R <= 4)
     for (int j0 = kb; j0 < k0; j0 += JG) {
         T l[JG][R];
