@@ -172,13 +172,31 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
 #pragma unroll
         for (int s = 0; s < S4; ++s) uf[t][s] = (s < 4 * nblk) ? up[4 * s] : T(0);
     }
-    // band solve, block by block
+    // the band's off-diagonal blocks L[block i2][block i] (i < i2), rows
+    // permuted by arow, all loaded here at once; a pair past nblk reads a
+    // block that exists (i clamped to nblk - 2, i2 to nblk - 1, the diagonal
+    // block when nblk == 1) and goes unused
+    constexpr int NP = NBLK * (NBLK - 1) / 2;
+    T lb[NP > 0 ? NP : 1][4];
 #pragma unroll
-    for (int i = 0; i < NBLK; ++i) {
+    for (int i = 0, q = 0; i < NBLK; ++i)
+#pragma unroll
+        for (int i2 = i + 1; i2 < NBLK; ++i2, ++q) {
+            const int ic = min(i, max(nblk - 2, 0)), i2c = min(i2, nblk - 1);
+            const T *lp = A + (size_t)(kb + 16 * ic + k4) * ld + kb + 16 * i2c + ar;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) lb[q][s] = lp[(size_t)(4 * s) * ld];
+        }
+    // band solve, block by block: X_i = linv_i Y_i, then Y_i2 += L_i2,i (-X_i)
+    // (the sign goes on X_i, which is in registers already, so the L blocks
+    // are used as loaded and their loads are waited for only where needed)
+#pragma unroll
+    for (int i = 0, q0 = 0; i < NBLK; q0 += NBLK - 1 - i, ++i) {
         if (i < nblk) {
             T li[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) li[s] = S.linv[slot0 + i][ar][4 * s + k4];
+            T xn[NT][4];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 acc_t acc;
@@ -187,22 +205,23 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
 #pragma unroll
                 for (int s = 0; s < 4; ++s) acc = mfma_t(li[s], uf[t][4 * i + s], acc);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) uf[t][4 * i + e] = acc[e];
+                for (int e = 0; e < 4; ++e) {
+                    uf[t][4 * i + e] = acc[e];
+                    xn[t][e] = -acc[e];
+                    asm volatile("" : "+v"(xn[t][e]));
+                }
             }
 #pragma unroll
             for (int i2 = i + 1; i2 < NBLK; ++i2) {
                 if (i2 < nblk) {
-                    T lf[4];   // -L[band block i2][band block i], rows permuted by arow
-                    const T *lp = A + (size_t)(kb + 16 * i + k4) * ld + kb + 16 * i2 + ar;
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) lf[s] = -lp[(size_t)(4 * s) * ld];
+                    const int q = q0 + (i2 - i - 1);
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
                         acc_t acc;
 #pragma unroll
                         for (int e = 0; e < 4; ++e) acc[e] = uf[t][4 * i2 + e];
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) acc = mfma_t(lf[s], uf[t][4 * i + s], acc);
+                        for (int s = 0; s < 4; ++s) acc = mfma_t(lb[q][s], xn[t][s], acc);
 #pragma unroll
                         for (int e = 0; e < 4; ++e) uf[t][4 * i2 + e] = acc[e];
                     }
