@@ -618,28 +618,37 @@ __device__ __forceinline__ void wave_linv(WaveLds<T> &S, int slot) {
 
 // ---- back substitution U x = y, y in LDS ------------------------------------
 // 64-row diagonal blocks from the bottom: lane = row, with the lane's row of
-// the block loaded into registers up front (one round trip), and the solved
-// entry of each step broadcast through a scalar register; then the rows
-// above take the block's contribution.
+// the block loaded into registers 32 columns at a time (one round trip each),
+// and the solved entry of each step broadcast through a scalar register; then
+// the rows above take the block's contribution, again 32 columns per round
+// trip.  (All 64 FP64 entries at once took 128 registers; the compiler then
+// spilled them and waited for each load on its own.)
 template <typename T, bool BATCH>
 __device__ __forceinline__ void wave_trsv_upper(const T *U, int ld, int n, T *y) {
+    constexpr int H = WL / 2;
     ld = opaque_s(ld);
     const int lane = wlane();
     for (int rb = ((n - 1) / WL) * WL; rb >= 0; rb -= WL) {
         const int w = min(WL, n - rb);
         const bool in = lane < w;
         const int r = rb + (in ? lane : 0);
-        T ub[WL];
-#pragma unroll
-        for (int j = 0; j < WL; ++j) ub[j] = U[(size_t)(rb + min(j, w - 1)) * ld + r];
         T yi = in ? y[r] : T(0);
         const T dinv = in ? T(1) / U[(size_t)r * ld + r] : T(0);
+        // the block's columns from the last down, the upper half first
+#pragma unroll 1
+        for (int h = 1; h >= 0; --h) {
+            const int j0 = H * h;
+            T ub[H];
 #pragma unroll
-        for (int j = WL - 1; j >= 0; --j) {
-            if (j < w) {
-                if (lane == j) yi *= dinv;
-                const T xj = readlane_t(yi, j);
-                if (lane < j) yi -= ub[j] * xj;
+            for (int j = 0; j < H; ++j) ub[j] = U[(size_t)(rb + min(j0 + j, w - 1)) * ld + r];
+#pragma unroll
+            for (int j = H - 1; j >= 0; --j) {
+                const int jj = j0 + j;
+                if (jj < w) {
+                    if (lane == jj) yi *= dinv;
+                    const T xj = readlane_t(yi, jj);
+                    if (lane < jj) yi -= ub[j] * xj;
+                }
             }
         }
         if (in) y[r] = yi;
@@ -648,15 +657,21 @@ __device__ __forceinline__ void wave_trsv_upper(const T *U, int ld, int n, T *y)
             const T *up = U + (size_t)rb * ld + rr;
             T s0 = y[rr], s1 = T(0);
             if constexpr (BATCH) {
-                // the row's 64 entries of the block in one round trip
+#pragma unroll 1
+                for (int j0 = 0; j0 < WL; j0 += H) {
+                    T ub[H];
 #pragma unroll
-                for (int j = 0; j < WL; ++j) ub[j] = up[(size_t)min(j, w - 1) * ld];
+                    for (int j = 0; j < H; ++j) ub[j] = up[(size_t)min(j0 + j, w - 1) * ld];
+                    // the block's solution, read from LDS here (hoisted out
+                    // of the loop it would hold 64 more registers)
+                    const T *yb = y + opaque_s(rb + j0);
 #pragma unroll
-                for (int j = 0; j < WL; j += 2) {
-                    const T x0 = (j < w) ? y[rb + j] : T(0);
-                    const T x1 = (j + 1 < w) ? y[rb + j + 1] : T(0);
-                    s0 -= ub[j] * x0;
-                    s1 -= ub[j + 1] * x1;
+                    for (int j = 0; j < H; j += 2) {
+                        const T x0 = (j0 + j < w) ? yb[j] : T(0);
+                        const T x1 = (j0 + j + 1 < w) ? yb[j + 1] : T(0);
+                        s0 -= ub[j] * x0;
+                        s1 -= ub[j + 1] * x1;
+                    }
                 }
             } else {
                 int j = 0;
