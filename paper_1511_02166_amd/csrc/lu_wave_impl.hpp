@@ -129,13 +129,20 @@ __device__ inline int lanes_below(unsigned long long m) {
 }
 
 template <typename T> struct WaveLds {
-    T l11[WNB][WNB + 1];     // unit-lower diagonal block of a pivot panel
     T linv[WSP / WNB][WNB][WNB + 1];   // inverses of the super-panel's diagonal blocks
     int mv_src[2 * WNB];     // row moves of the last panel: row mv_src[m]
     int mv_dst[2 * WNB];     //   ends at position mv_dst[m]
     int nmv;
     int ipiv[WNB];           // LAPACK pivots of the last panel (positions)
-    T ub[WSP - WNB][WNB];    // U rows of the next panel's columns (left-looking step)
+    // The pivot panels' buffers and the U tile of a super-panel's trailing
+    // update are never in use at the same time: they share their memory.
+    union {
+        struct {
+            T l11[WNB][WNB + 1];     // unit-lower diagonal block of a pivot panel
+            T ub[WSP - WNB][WNB];    // U rows of the next panel's columns (left-looking step)
+        };
+        T ut[WSP / 4][WL];           // -U of one 16-column tile, A-operand order (k-step, lane)
+    };
 };
 
 // ---- block update after pivot panels: band solve + trailing product --------
@@ -155,10 +162,14 @@ template <typename T> struct WaveLds {
 // past n / columns past c1 are clamped for the loads and never stored; rows
 // of the band past n are zero padding (linv is the identity there).
 // One chunk of NT 16-column tiles starting at column cs (columns past c1
-// are clamped for the loads and never stored).
-template <typename T, int NBLK, int NT, bool TRAIL = true>
+// are clamped for the loads and never stored).  With NL = 1 the trailing
+// product also updates the tile of columns [cf, c1) (at most 16, whose band
+// rows have been solved already) with its -U fragments in LDS: the last
+// narrow tile of a block rides with the last full chunk instead of making a
+// pass over L of its own.
+template <typename T, int NBLK, int NT, bool TRAIL = true, int NL = 0>
 __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int kend, int cs, int c1,
-                                             const WaveLds<T> &S, int slot0, int nblk) {
+                                             WaveLds<T> &S, int slot0, int nblk, int cf = 0) {
     ld = opaque_s(ld);
     constexpr int S4 = 4 * NBLK;   // k-steps (4 rows each) of the band
     typedef typename TileMap<T>::acc acc_t;
@@ -253,18 +264,27 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
             uf[t][s] = -uf[t][s];
             asm volatile("" : "+v"(uf[t][s]));   // keep the flip here, not at each use
         }
-    int coff[NT][4];   // element offsets of this lane's C columns (clamped)
-    bool cok[NT][4];
+    static_assert(NL == 0 || NL == 1, "at most one tile in LDS");
+    if constexpr (NL == 1) {
+        const int c = min(cf + i16, c1 - 1);
+        const T *up = A + (size_t)c * ld + kb + k4;
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+        for (int s = 0; s < S4; ++s) S.ut[s][lane] = (s < 4 * nblk) ? -up[4 * s] : T(0);
+        wave_sync();
+    }
+    constexpr int NU = NT + NL;   // tiles of the trailing product
+    int coff[NU][4];   // element offsets of this lane's C columns (clamped)
+    bool cok[NU][4];
+#pragma unroll
+    for (int t = 0; t < NU; ++t)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int c = cs + 16 * t + TileMap<T>::col(lane, e);
+            const int c = (t < NT ? cs + 16 * t : cf) + TileMap<T>::col(lane, e);
             cok[t][e] = c < c1;
             coff[t][e] = min(c, c1 - 1) * ld;
         }
     const T *lcol = A + (size_t)(kb + k4) * ld;
-    if constexpr (NBLK == 1 || (NT == 1 && NBLK <= 3)) {
+    if constexpr (NL == 0 && (NBLK == 1 || (NT == 1 && NBLK <= 3))) {
         // little work per tile (at most 12 dependent products): D tiles in
         // flight; each step computes one tile and issues the loads of the
         // tile D - 1 ahead into the slot just freed
@@ -310,12 +330,12 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
         // into the register this tile's product has just consumed.  Every
         // wait is then for loads issued about one tile earlier.
         T lf[S4];
-        T cb[NT][4];
+        T cb[NU][4];
         const int rc = min(kend + i16, n - 1);
 #pragma unroll
         for (int s = 0; s < S4; ++s) lf[s] = lcol[(size_t)(4 * s) * ld + rc];
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NU; ++t)
 #pragma unroll
             for (int e = 0; e < 4; ++e) cb[t][e] = A[coff[t][e] + rc];
         // the first tile's operands complete here, so that inside the loop
@@ -325,26 +345,30 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
         for (int rt = kend; rt < n; rt += 16) {
             const int r = rt + i16;
             const int rn = min(r + 16, n - 1);   // next tile's row (clamped)
-            acc_t acc[NT];
+            acc_t acc[NU];
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int t = 0; t < NU; ++t)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) acc[t][e] = T(0);
+            // the LDS tile is read in the loop (hoisted out of it, its 16
+            // fragments would take the registers of a fourth tile)
+            const T *ut = &S.ut[0][lane] + opaque_s(0);
 #pragma unroll
             for (int s = 0; s < S4; ++s) {
 #pragma unroll
                 for (int t = 0; t < NT; ++t) acc[t] = mfma_t(uf[t][s], lf[s], acc[t]);
+                if constexpr (NL == 1) acc[NT] = mfma_t(ut[s * WL], lf[s], acc[NT]);
                 lf[s] = lcol[(size_t)(4 * s) * ld + rn];
             }
             if (r < n) {
 #pragma unroll
-                for (int t = 0; t < NT; ++t)
+                for (int t = 0; t < NU; ++t)
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
                         if (cok[t][e]) A[coff[t][e] + r] = cb[t][e] + acc[t][e];
             }
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int t = 0; t < NU; ++t)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) cb[t][e] = A[coff[t][e] + rn];
         }
@@ -355,7 +379,7 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
 // left (1 .. R), so it makes one pass over L like a full chunk.
 template <typename T, int NBLK, int R>
 __device__ __forceinline__ void update_rest(int tiles, T *A, int ld, int n, int kb, int kend, int cs, int c1,
-                                            const WaveLds<T> &S, int slot0, int nblk) {
+                                            WaveLds<T> &S, int slot0, int nblk) {
     if constexpr (R >= 1) {
         if (tiles == R)
             update_chunk<T, NBLK, R>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
@@ -366,7 +390,7 @@ __device__ __forceinline__ void update_rest(int tiles, T *A, int ld, int n, int 
 
 template <typename T, int NBLK>
 __device__ __forceinline__ void wave_update(T *A, int ld, int n, int kb, int kend, int c0, int c1,
-                                            const WaveLds<T> &S, int slot0) {
+                                            WaveLds<T> &S, int slot0) {
     constexpr int NTM = Wct<T>::v / 16;
     const int nblk = min(NBLK, (kend - kb + WNB - 1) / WNB);
     // full chunks, then one of the remaining width (a trailing block of
@@ -375,6 +399,19 @@ __device__ __forceinline__ void wave_update(T *A, int ld, int n, int kb, int ken
     // free of scratch spills)
     constexpr int RM = sizeof(T) == 8 ? NTM - 1 : 2;
     int cs = c0;
+    const int nfull = (c1 - c0) / (16 * NTM), rest = c1 - c0 - 16 * NTM * nfull;
+    if (nfull >= 1 && rest > 0 && rest <= 16) {
+        // a last tile of at most 16 columns (often the last matrix column and
+        // the right-hand sides) rides with the last full chunk: its band rows
+        // are solved first, on their own
+        const int cf = c0 + 16 * NTM * nfull;
+        update_chunk<T, NBLK, 1, false>(A, ld, n, kb, kend, cf, c1, S, slot0, nblk);
+        wave_sync();
+        for (; cs + 16 * NTM < cf; cs += 16 * NTM)
+            update_chunk<T, NBLK, NTM>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
+        update_chunk<T, NBLK, NTM, true, 1>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk, cf);
+        return;
+    }
     for (; c1 - cs > 16 * (NTM - 1); cs += 16 * NTM)
         update_chunk<T, NBLK, NTM>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
     while (cs < c1) {
