@@ -609,25 +609,47 @@ __device__ __forceinline__ void wave_panel(T *A, int ld, int n, int k0, int nb, 
 }
 
 // ---- apply the panel's row moves to every column outside it ----------------
+// M loads per column, issued together whatever nmv (<= M) is: moves past
+// nmv repeat the last one, which reads and writes the same element with the
+// same value.  (Each load under its own m < nmv test went into a branch of
+// its own and was waited for there, one memory latency per move.)
+template <typename T, int M>
+__device__ __forceinline__ void wave_moves_m(T *A, int ld, int ncols, int k0, int nb, int nmv,
+                                             const WaveLds<T> &S) {
+    const int lane = wlane();
+    int src[M], dst[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int mm = min(m, nmv - 1);
+        src[m] = S.mv_src[mm];
+        dst[m] = S.mv_dst[mm];
+    }
+#pragma unroll 1
+    for (int j = lane; j < ncols; j += WL) {
+        if (j >= k0 && j < k0 + nb) continue;
+        T *cp = A + (size_t)j * ld;
+        T t[M];
+        // every element read before any is written (a row may be both the
+        // source of one move and the destination of another)
+#pragma unroll
+        for (int m = 0; m < M; ++m) t[m] = cp[src[m]];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) cp[dst[m]] = t[m];
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void wave_moves(T *A, int ld, int ncols, int k0, int nb, const WaveLds<T> &S) {
     const int nmv = __builtin_amdgcn_readfirstlane(S.nmv);
     if (nmv == 0) return;
     ld = opaque_s(ld);
-    const int lane = wlane();
-#pragma unroll 1
-    for (int j = lane; j < ncols; j += WL) {
-        if (j >= k0 && j < k0 + nb) continue;
-        T *cp = A + (size_t)j * ld;
-        T t[2 * WNB];
-#pragma unroll
-        for (int m = 0; m < 2 * WNB; ++m)
-            if (m < nmv) t[m] = cp[S.mv_src[m]];
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int m = 0; m < 2 * WNB; ++m)
-            if (m < nmv) cp[S.mv_dst[m]] = t[m];
-    }
+    if (nmv <= 2)
+        wave_moves_m<T, 2>(A, ld, ncols, k0, nb, nmv, S);
+    else if (nmv <= 8)
+        wave_moves_m<T, 8>(A, ld, ncols, k0, nb, nmv, S);
+    else
+        wave_moves_m<T, 2 * WNB>(A, ld, ncols, k0, nb, nmv, S);
 }
 
 // ---- inverse of the panel's unit-lower diagonal block: linv = l11^{-1} -----

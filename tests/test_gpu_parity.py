@@ -522,6 +522,77 @@ def test_chord_and_freestream_speed(precision, wave_limit):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_heavy_pivoting_dense_systems(precision):
+    # Panel systems hardly pivot (the Kutta row swaps twice), so the row moves
+    # of the wavefront LU are exercised here on dense systems written over the
+    # assembled ones in the workspace (its documented layout): Gaussian entries
+    # pivot at nearly every step (up to 32 rows moved per 16-column panel), a
+    # Gaussian matrix plus a diagonal shift of 6 at some (0, 2, 4 and 17 to 22
+    # rows per panel), one shifted by 40 at none.  Checks P A = L U with every
+    # multiplier |l| <= 1 (the partial-pivoting property) and the solutions
+    # against the oracle's LU, within 64 eps times the condition number.
+    import paper_1511_02166_amd as P
+    torch = _torch()
+    sizes = [255, 130, 200]
+    _say(f"heavy pivoting, precision={precision}, N={sizes}")
+    xy_flat, noff = synth.joukowski_batch(5, len(sizes), sizes)
+    aoff = np.arange(len(sizes) + 1, dtype=np.int32) * 2
+    s = P.PanelSolver(noff, aoff, precision)
+    xy = torch.as_tensor(xy_flat, device="cuda")
+    s.assemble(xy, torch.as_tensor(np.tile([0.02, 0.15], len(sizes)), device="cuda"))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(71)
+    mats = []
+    for b, N in enumerate(sizes):
+        n = N + 1
+        d = s.plan.layout(b)
+        ld, K = d["ld"], d["K"]
+        A = rng.standard_normal((n, n)) + (0.0, 6.0, 40.0)[b] * np.eye(n)
+        R = rng.standard_normal((K, n))
+        full = np.zeros((n + K, ld))
+        full[:n, :n] = A.T          # column-major: row j of `full` is column j
+        full[n:, :n] = R
+        s.ws[d["a64"]:d["a64"] + 8 * full.size].copy_(
+            torch.as_tensor(full.reshape(-1)).view(torch.uint8))
+        if precision == 1:
+            s.ws[d["a32"]:d["a32"] + 4 * full.size].copy_(
+                torch.as_tensor(full.reshape(-1).astype(np.float32)).view(torch.uint8))
+        mats.append((A, R))
+    s.factor_solve()
+    torch.cuda.synchronize()
+    assert np.all(s.info.cpu().numpy() == 0)
+    moved = []
+    for b, N in enumerate(sizes):
+        n = N + 1
+        A, R = mats[b]
+        d = s.plan.layout(b)
+        LU, _ = s.system(b, "a64" if precision == 0 else "a32")
+        LU = LU.astype(np.float64)
+        piv = s.pivots(b)
+        PA = A.copy()
+        for i in range(n):
+            assert i <= piv[i] < n
+            PA[[i, piv[i]]] = PA[[piv[i], i]]
+        Lm = np.tril(LU, -1) + np.eye(n)
+        tol = 1e-13 if precision == 0 else 2e-6
+        res = np.max(np.abs(PA - Lm @ np.triu(LU))) / np.max(np.abs(A))
+        assert res < tol * n, (b, res)
+        assert np.max(np.abs(np.tril(LU, -1))) <= 1.0 + 1e-12, b
+        moved.append(int(np.sum(piv != np.arange(n))))
+        X = s.ws[d["x"]:d["x"] + 8 * d["K"] * n].view(torch.float64).cpu().numpy().reshape(d["K"], n)
+        oLU, opiv, oinfo = oracle.lu(A)
+        assert oinfo == 0
+        Xo = oracle.lu_solve(oLU, opiv, R)
+        err = np.max(np.abs(X - Xo)) / np.max(np.abs(Xo))
+        kappa = np.linalg.cond(A, np.inf)
+        bound = max(1e-11 if precision == 0 else 1e-9, 64 * np.finfo(np.float64).eps * kappa)
+        _say(f"  N={N}: rows moved {moved[-1]}, |PA-LU|/|A| {res:.1e}, solution error {err:.1e}"
+             f" (bound {bound:.1e})")
+        assert err < bound, (b, err, bound)
+    assert moved[0] > 0.8 * sizes[0] and 0 < moved[1] < moved[0] and moved[2] == 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("wave_limit", [None, 0])
 def test_exact_zero_pivot_reports_column(precision, wave_limit):
     # An exactly singular system: the assembled matrix of airfoil 1 with one
