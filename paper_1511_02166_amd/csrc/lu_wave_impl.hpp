@@ -398,7 +398,9 @@ __device__ __forceinline__ void wave_update(T *A, int ld, int n, int kb, int ken
     // (FP32: at most two tiles at a time in the rest, which keeps the kernel
     // free of scratch spills)
     constexpr int RM = sizeof(T) == 8 ? NTM - 1 : 2;
-    int cs = c0;
+    // The chunks go from the right end to the left: the leftmost columns,
+    // which the next super-panel's panels read first, are written last and
+    // are then more likely still in the caches.
     const int nfull = (c1 - c0) / (16 * NTM), rest = c1 - c0 - 16 * NTM * nfull;
     if (nfull >= 1 && rest > 0 && rest <= 16) {
         // a last tile of at most 16 columns (often the last matrix column and
@@ -407,18 +409,21 @@ __device__ __forceinline__ void wave_update(T *A, int ld, int n, int kb, int ken
         const int cf = c0 + 16 * NTM * nfull;
         update_chunk<T, NBLK, 1, false>(A, ld, n, kb, kend, cf, c1, S, slot0, nblk);
         wave_sync();
-        for (; cs + 16 * NTM < cf; cs += 16 * NTM)
-            update_chunk<T, NBLK, NTM>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
+        int cs = cf - 16 * NTM;
         update_chunk<T, NBLK, NTM, true, 1>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk, cf);
+        for (cs -= 16 * NTM; cs >= c0; cs -= 16 * NTM)
+            update_chunk<T, NBLK, NTM>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
         return;
     }
-    for (; c1 - cs > 16 * (NTM - 1); cs += 16 * NTM)
-        update_chunk<T, NBLK, NTM>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
-    while (cs < c1) {
+    int ce = c0;   // end of the full chunks (the last may run past c1, clamped)
+    while (c1 - ce > 16 * (NTM - 1)) ce += 16 * NTM;
+    for (int cs = ce; cs < c1;) {
         const int tiles = min(RM, (c1 - cs + 15) / 16);
         update_rest<T, NBLK, RM>(tiles, A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
         cs += 16 * tiles;
     }
+    for (int cs = ce - 16 * NTM; cs >= c0; cs -= 16 * NTM)
+        update_chunk<T, NBLK, NTM>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
 }
 
 // ---- one column step of the panel factorisation (C is compile-time) --------
