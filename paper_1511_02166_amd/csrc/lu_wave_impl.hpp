@@ -169,7 +169,7 @@ template <typename T> struct WaveLds {
 // pass over L of its own.
 template <typename T, int NBLK, int NT, bool TRAIL = true, int NL = 0>
 __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int kend, int cs, int c1,
-                                             WaveLds<T> &S, int slot0, int nblk, int cf = 0) {
+                                             WaveLds<T> &S, int slot0, int nblk, int cf = 0, int up = 0) {
     ld = opaque_s(ld);
     constexpr int S4 = 4 * NBLK;   // k-steps (4 rows each) of the band
     typedef typename TileMap<T>::acc acc_t;
@@ -329,9 +329,13 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
         // right after this tile's stores, each L fragment of the next tile
         // into the register this tile's product has just consumed.  Every
         // wait is then for loads issued about one tile earlier.
+        // the row tiles downwards, or upwards when up != 0 (consecutive chunks
+        // alternate, so each starts on the L tiles the one before ended on)
+        const int ntile = (n - kend + 15) / 16, step = up ? -16 : 16;
+        const int rt0 = up ? kend + 16 * (ntile - 1) : kend;
         T lf[S4];
         T cb[NU][4];
-        const int rc = min(kend + i16, n - 1);
+        const int rc = min(rt0 + i16, n - 1);
 #pragma unroll
         for (int s = 0; s < S4; ++s) lf[s] = lcol[(size_t)(4 * s) * ld + rc];
 #pragma unroll
@@ -342,9 +346,9 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
         // only the loop's own issue order decides what each product waits for
 #pragma unroll
         for (int s = 0; s < S4; ++s) asm volatile("" ::"v"(lf[s]));
-        for (int rt = kend; rt < n; rt += 16) {
+        for (int it = 0, rt = rt0; it < ntile; ++it, rt += step) {
             const int r = rt + i16;
-            const int rn = min(r + 16, n - 1);   // next tile's row (clamped)
+            const int rn = min(max(r + step, kend), n - 1);   // next tile's row (clamped)
             acc_t acc[NU];
 #pragma unroll
             for (int t = 0; t < NU; ++t)
@@ -379,12 +383,12 @@ __device__ __forceinline__ void update_chunk(T *A, int ld, int n, int kb, int ke
 // left (1 .. R), so it makes one pass over L like a full chunk.
 template <typename T, int NBLK, int R>
 __device__ __forceinline__ void update_rest(int tiles, T *A, int ld, int n, int kb, int kend, int cs, int c1,
-                                            WaveLds<T> &S, int slot0, int nblk) {
+                                            WaveLds<T> &S, int slot0, int nblk, int up) {
     if constexpr (R >= 1) {
         if (tiles == R)
-            update_chunk<T, NBLK, R>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
+            update_chunk<T, NBLK, R>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk, 0, up);
         else
-            update_rest<T, NBLK, R - 1>(tiles, A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
+            update_rest<T, NBLK, R - 1>(tiles, A, ld, n, kb, kend, cs, c1, S, slot0, nblk, up);
     }
 }
 
@@ -409,21 +413,27 @@ __device__ __forceinline__ void wave_update(T *A, int ld, int n, int kb, int ken
         const int cf = c0 + 16 * NTM * nfull;
         update_chunk<T, NBLK, 1, false>(A, ld, n, kb, kend, cf, c1, S, slot0, nblk);
         wave_sync();
-        int cs = cf - 16 * NTM;
-        update_chunk<T, NBLK, NTM, true, 1>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk, cf);
-        for (cs -= 16 * NTM; cs >= c0; cs -= 16 * NTM)
-            update_chunk<T, NBLK, NTM>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
+        int cs = cf - 16 * NTM, up = 0;
+        update_chunk<T, NBLK, NTM, true, 1>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk, cf, up);
+        for (cs -= 16 * NTM; cs >= c0; cs -= 16 * NTM) {
+            up ^= 1;
+            update_chunk<T, NBLK, NTM>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk, 0, up);
+        }
         return;
     }
     int ce = c0;   // end of the full chunks (the last may run past c1, clamped)
     while (c1 - ce > 16 * (NTM - 1)) ce += 16 * NTM;
+    int up = 1;
     for (int cs = ce; cs < c1;) {
         const int tiles = min(RM, (c1 - cs + 15) / 16);
-        update_rest<T, NBLK, RM>(tiles, A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
+        up ^= 1;
+        update_rest<T, NBLK, RM>(tiles, A, ld, n, kb, kend, cs, c1, S, slot0, nblk, up);
         cs += 16 * tiles;
     }
-    for (int cs = ce - 16 * NTM; cs >= c0; cs -= 16 * NTM)
-        update_chunk<T, NBLK, NTM>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk);
+    for (int cs = ce - 16 * NTM; cs >= c0; cs -= 16 * NTM) {
+        up ^= 1;
+        update_chunk<T, NBLK, NTM>(A, ld, n, kb, kend, cs, c1, S, slot0, nblk, 0, up);
+    }
 }
 
 // ---- one column step of the panel factorisation (C is compile-time) --------
