@@ -156,11 +156,12 @@ template <typename T> struct WaveLds {
 // 16-column tile), solved in registers block by block on the matrix cores
 // (X_i = linv_i Y_i, then Y_j -= L_ji X_i), stored once, and kept as the U
 // fragments of the trailing product.  The trailing product streams 16-row
-// tiles of L and C; the next tile's loads are interleaved with the current
-// tile's products (its C block into a second accumulator set, each L
-// fragment into the register the current product has just consumed).  Rows
-// past n / columns past c1 are clamped for the loads and never stored; rows
-// of the band past n are zero padding (linv is the identity there).
+// tiles of L and C, downwards or upwards (`up`): each L fragment of the next
+// tile goes into the register the current tile's product has just consumed,
+// the products start from zero and the tile's C block, loaded after the
+// previous tile's stores, is added after them.  Rows past n / columns past
+// c1 are clamped for the loads and never stored; rows of the band past n are
+// zero padding (linv is the identity there).
 // One chunk of NT 16-column tiles starting at column cs (columns past c1
 // are clamped for the loads and never stored).  With NL = 1 the trailing
 // product also updates the tile of columns [cf, c1) (at most 16, whose band
