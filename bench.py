@@ -55,7 +55,7 @@ ADJ_FLOPS_PER_PAIR = 167.0
 # batch, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's
 # readings (x2.0 and x1.0).  Valid only for the kernel source it was taken
 # on, which is identified by the SHA-256 prefix of that source file.
-LU_TRAFFIC = {("lu_wave_impl.hpp", "dfbe239bfdcdbb4e"): 8_134_936_992}   # one wavefront per airfoil
+LU_TRAFFIC = {("lu_wave_impl.hpp", "fee324e394c1c5ea"): 8_143_239_712}   # one wavefront per airfoil
 
 # Host threads for the oracle: at most 16, the host cores a benchmark node gives each GPU.
 CPU_SHARE = 16
